@@ -1,0 +1,366 @@
+"""Trace-level pins of the oracle against closed-form physics (CPU only).
+
+* Exact capture criterion: a ray from the observer is captured iff the radial
+  potential R(r) of its conserved (xi, eta) has no root between the horizon
+  and the observer (Kerr separability; independent of the integrator).
+* Schwarzschild shadow radius 3 sqrt(3) M (the critical impact parameter the
+  paper quotes in Sec. 4.1), seen from D = 1000 M as 3 sqrt(3) sqrt(1 - 2/D).
+* Bardeen critical curve (Sec. 4.2): rays just inside it are captured, just
+  outside escape.
+* Schwarzschild equatorial deflection angle from an independent quadrature.
+* The paper's constraint experiments (Sec. 4.1): |H| <~ 1e-9 for the escaping
+  b = 6 ray at rtol = atol = 1e-10, and growth of |H| toward the horizon for
+  the captured b = 3 ray stopped at 2.05 M.
+* Conservation: E and L bit-exact; Carter's constant to the tolerance.
+* Tolerance convergence, and a fixed-step RK4 brute-force cross-check of the
+  disk-crossing radius and affine parameter.
+* Qualitative: the approaching side of the disk is brighter (Sec. 2.4, Sec. 4.2).
+* Tabulated metric: exact on bicubic data, fourth-order grid convergence.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+import json
+import os
+
+import workloads as W
+
+D = 1000.0
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def conserved(q, a, iota):
+    E, L = q[4], -q[7]
+    Q = q[6] ** 2 + math.cos(iota) ** 2 * (L * L / math.sin(iota) ** 2 - a * a * E * E)
+    return E, L, Q
+
+
+def captured_exact(a, xi, eta, r_obs, rp):
+    """Captured iff R(r) = (r^2 + a^2 - a xi)^2 - Delta (eta + (xi - a)^2) has no real root in (r_+, r_obs)."""
+    c4 = 1.0
+    # expand R(r) as a quartic in r
+    A = a * a - a * xi
+    K = eta + (xi - a) ** 2
+    coeffs = [c4, 0.0, 2 * A - K, 2 * K, A * A - a * a * K]
+    roots = np.roots(coeffs)
+    real = roots[np.abs(roots.imag) < 1e-9 * np.maximum(1, np.abs(roots.real))].real
+    return not np.any((real > rp) & (real < r_obs))
+
+
+def edge_band(cls2d):
+    """Pixels with an 8-neighbour of a different class."""
+    band = np.zeros_like(cls2d, dtype=bool)
+    H, Wd = cls2d.shape
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            if di == 0 and dj == 0:
+                continue
+            sh = np.full_like(cls2d, -99)
+            ys = slice(max(0, dj), H + min(0, dj))
+            yd = slice(max(0, -dj), H + min(0, -dj))
+            xs = slice(max(0, di), Wd + min(0, di))
+            xd = slice(max(0, -di), Wd + min(0, -di))
+            sh[yd, xd] = cls2d[ys, xs]
+            band |= (sh != cls2d) & (sh != -99)
+    return band
+
+
+@pytest.mark.parametrize("a,th_deg,nx,w", [(0.0, 90.0, 64, 10.0), (0.9, 60.0, 40, 12.0), (0.998, 17.0, 40, 10.0)])
+def test_capture_matches_exact_criterion(orc, a, th_deg, nx, w):
+    c = W.camera(D, th_deg, nx, nx, w)
+    m = orc.make_metric(a)
+    o = orc.trace(m, orc.make_camera(c), orc.make_disk(None), orc.make_solver(W.solver()))
+    cls = o["cls"].reshape(nx, nx)
+    assert not np.any(cls == orc.FAILED)
+    rp = orc.horizon(a)
+    ca = orc.make_camera(c)
+    exact = np.zeros_like(cls)
+    for j in range(nx):
+        for i in range(nx):
+            q = orc.initial_state(m, ca, i, j)
+            E, L, Q = conserved(q, a, c["theta_obs"])
+            exact[j, i] = 1 if captured_exact(a, L / E, Q / E ** 2, D, rp) else 0
+    band = edge_band(exact)
+    assert np.array_equal(cls[~band], exact[~band])
+    assert band.mean() < 0.2
+
+
+def single_ray(orc, a, th_deg, alpha, beta, solver=None, disk=None):
+    c = dict(r_obs=D, theta_obs=th_deg * math.pi / 180, nx=1, ny=1,
+             alpha_min=alpha, alpha_max=alpha, beta_min=beta, beta_max=beta)
+    return orc.trace(orc.make_metric(a), orc.make_camera(c), orc.make_disk(disk),
+                     orc.make_solver(solver or W.solver()))
+
+
+def test_schwarzschild_shadow_radius(orc):
+    lo, hi = 5.0, 5.4  # captured at lo, escapes at hi
+    assert single_ray(orc, 0.0, 90.0, lo, 0.0)["cls"][0] == orc.CAPTURED
+    assert single_ray(orc, 0.0, 90.0, hi, 0.0)["cls"][0] == orc.ESCAPED
+    for _ in range(24):
+        mid = 0.5 * (lo + hi)
+        if single_ray(orc, 0.0, 90.0, mid, 0.0)["cls"][0] == orc.CAPTURED:
+            lo = mid
+        else:
+            hi = mid
+    rho = GOLDEN["critical_impact_parameter"]["value"] * math.sqrt(1 - 2 / D)
+    assert rho == pytest.approx(5.190953670, abs=1e-9)
+    assert 0.5 * (lo + hi) == pytest.approx(rho, abs=2e-6)
+
+
+def bardeen_curve(a, iota, n=24):
+    """Critical curve from spherical photon orbits (Bardeen 1973), at infinity."""
+    rph_p = 2 * (1 + math.cos(2 / 3 * math.acos(-a)))
+    rph_m = 2 * (1 + math.cos(2 / 3 * math.acos(a)))
+    r = np.linspace(rph_p, rph_m, n + 2)[1:-1]
+    xi = (r * r * (3 - r) - a * a * (r + 1)) / (a * (r - 1))
+    eta = r ** 3 * (4 * a * a - r * (r - 3) ** 2) / (a * a * (r - 1) ** 2)
+    b2 = eta + a * a * math.cos(iota) ** 2 - xi ** 2 / math.tan(iota) ** 2
+    ok = b2 > 0
+    return list(zip(-xi[ok] / math.sin(iota), np.sqrt(b2[ok])))
+
+
+def test_bardeen_critical_curve_separates_classes(orc):
+    a, th = 0.9, 60.0
+    iota = th * math.pi / 180
+    pts = bardeen_curve(a, iota, 10)
+    al = [p[0] for p in pts]
+    assert min(al) == pytest.approx(-3.0959, abs=2e-3) or min(al) > -3.0959
+    s = math.sqrt(1 - 2 / D)
+    cx = 0.5 * (max(al) + min(al))
+    for aB, bB in pts[::2]:
+        for sign in (1, -1):
+            x, y = aB * s, sign * bB * s
+            inside = single_ray(orc, a, th, cx + (x - cx) * 0.99, y * 0.99)["cls"][0]
+            outside = single_ray(orc, a, th, cx + (x - cx) * 1.01, y * 1.01)["cls"][0]
+            assert inside == orc.CAPTURED and outside == orc.ESCAPED
+
+
+def test_bardeen_curve_extents():
+    # numbers quoted for the scenes (a = 0.9, i = 60 deg; a = 0.998, i = 17 deg)
+    for a, th, amin, amax, bmax in [(0.9, 60.0, -3.0959, 6.5894, 5.1355), (0.998, 17.0, -4.0922, 5.5077, 4.8712)]:
+        pts = bardeen_curve(a, th * math.pi / 180, 400000)
+        al = np.array([p[0] for p in pts])
+        be = np.array([p[1] for p in pts])
+        assert al.min() == pytest.approx(amin, abs=2e-3)
+        assert al.max() == pytest.approx(amax, abs=2e-3)
+        assert be.max() == pytest.approx(bmax, abs=2e-3)
+
+
+@pytest.mark.parametrize("alpha", [6.5, 9.0, 15.0])
+def test_schwarzschild_deflection_quadrature(orc, alpha):
+    """Equatorial escape: total phi swept between r = 1000 (start) and r = 1100 (stop)."""
+    b = alpha / math.sqrt(1 - 2 / D)
+    P = lambda u: 1 / b ** 2 - u * u + 2 * u ** 3
+    roots = np.roots([2.0, -1.0, 0.0, 1 / b ** 2])
+    ut = min(r.real for r in roots if abs(r.imag) < 1e-12 and r.real > 0)
+
+    def leg(u0):
+        # substitute u = ut - s^2 to remove the turning-point singularity
+        return quad(lambda s: 2 * s / math.sqrt(max(P(ut - s * s), 1e-300)), 1e-12, math.sqrt(ut - u0),
+                    epsabs=1e-13, epsrel=1e-13, limit=400)[0]
+
+    expect = leg(1 / D) + leg(1 / 1100.0)
+    o = single_ray(orc, 0.0, 90.0, alpha, 0.0, solver=W.solver(rtol=1e-12, atol=1e-14))
+    assert o["cls"][0] == orc.ESCAPED
+    assert abs(o["final_rtp"][0, 2]) == pytest.approx(expect, rel=2e-9)
+    assert o["final_rtp"][0, 0] == pytest.approx(1100.0, abs=1e-9)
+    assert o["final_rtp"][0, 1] == pytest.approx(math.pi / 2, abs=1e-12)
+
+
+def paper_ray(orc, b, r0, solver, disk=None):
+    """A Schwarzschild ray launched from r0 = D in the equatorial plane with impact parameter b."""
+    c = dict(r_obs=r0, theta_obs=math.pi / 2, nx=1, ny=1, alpha_min=b * math.sqrt(1 - 2 / r0),
+             alpha_max=b * math.sqrt(1 - 2 / r0), beta_min=0.0, beta_max=0.0)
+    m = orc.make_metric(0.0)
+    q0 = orc.initial_state(m, orc.make_camera(c), 0, 0)
+    return orc.trace_path(m, q0, 0.01 * r0, orc.make_disk(disk), orc.make_solver(solver)), m
+
+
+def test_paper_escaping_ray_constraint(orc):
+    """Sec. 4.1: b = 6 from r0 = 100 M, atol = rtol = 1e-10: the RK pairs hold |H| <~ 1e-9."""
+    g = GOLDEN["escaping_ray"]
+    p, m = paper_ray(orc, g["b"], g["r0"], W.solver(rtol=g["rtol"], atol=g["atol"], r_escape=1000.0))
+    assert p["cls"] == orc.ESCAPED
+    H = np.array([abs(orc.hamiltonian(m, q)) for q in p["states"]])
+    assert H.max() < g["max_eps_H_rk_pairs"]
+    assert p["h_drift"] == pytest.approx(H.max(), rel=0, abs=0)
+    rmin = p["states"][:, 1].min()
+    assert 3.0 < rmin < 6.0  # dives into the strong field (turning point of b = 6 is 4.41 M)
+
+
+def test_paper_captured_ray_constraint_grows(orc):
+    """Sec. 4.1: b = 3 plunges; stopped at r = 2.05 M the residual grows toward the horizon."""
+    g = GOLDEN["captured_ray"]
+    p, m = paper_ray(orc, g["b"], g["r0"], W.solver(rtol=g["rtol"], atol=g["atol"], horizon_factor=g["r_stop"] / 2.0))
+    assert p["cls"] == orc.CAPTURED
+    assert p["final_rtp"][0] == pytest.approx(g["r_stop"], abs=1e-9)
+    H = np.array([abs(orc.hamiltonian(m, q)) for q in p["states"]])
+    r = p["states"][:, 1]
+    assert H[r < 3.0].max() > 10 * H[r > 20.0].max()
+
+
+def test_conservation_along_kerr_ray(orc):
+    a, th = 0.9, 60.0
+    iota = th * math.pi / 180
+    m = orc.make_metric(a)
+    c = dict(r_obs=D, theta_obs=iota, nx=1, ny=1, alpha_min=-4.0, alpha_max=-4.0, beta_min=6.0, beta_max=6.0)
+    q0 = orc.initial_state(m, orc.make_camera(c), 0, 0)
+    p = orc.trace_path(m, q0, 10.0, orc.make_disk(dict(r_out=20.0)),
+                       orc.make_solver(W.solver(rtol=1e-10, atol=1e-12)))
+    st = p["states"]
+    assert np.all(st[:, 4] == q0[4]) and np.all(st[:, 7] == q0[7])  # E, L bit-exact
+    E, L, Q0 = conserved(q0, a, iota)
+    Qs = st[:, 6] ** 2 + np.cos(st[:, 2]) ** 2 * (L * L / np.sin(st[:, 2]) ** 2 - a * a * E * E)
+    assert np.abs(Qs / Q0 - 1).max() < 1e-7
+    assert p["n_hits"] >= 1
+
+
+def disk_pixels():
+    return [(-6.0, 4.0), (7.0, -3.0), (-12.0, 0.5), (3.0, 9.0), (-2.0, -5.5), (10.0, 10.0)]
+
+
+def test_tolerance_convergence(orc):
+    a, th = 0.9, 60.0
+    res = {}
+    for rtol in (1e-8, 1e-10, 1e-12):
+        res[rtol] = [single_ray(orc, a, th, al, be, solver=W.solver(rtol=rtol, atol=rtol / 100),
+                                disk=dict(r_out=20.0)) for al, be in disk_pixels()]
+    d8 = d10 = 0.0
+    for k in range(len(disk_pixels())):
+        r12 = res[1e-12][k]
+        assert res[1e-8][k]["n_hits"][0] == r12["n_hits"][0] >= 1
+        n = r12["n_hits"][0]
+        d8 = max(d8, np.abs(res[1e-8][k]["hit_r"][0, :n] / r12["hit_r"][0, :n] - 1).max())
+        d10 = max(d10, np.abs(res[1e-10][k]["hit_r"][0, :n] / r12["hit_r"][0, :n] - 1).max())
+    # the global error shrinks with the tolerance (it is ~1e-6 relative at rtol = 1e-8)
+    assert d10 < d8 / 5 and d8 < 1e-5 and d10 < 1e-6
+
+
+def test_rk4_brute_force_crossing(orc):
+    """Disk-crossing radius of the adaptive oracle against fixed-step RK4 at two step sizes."""
+    a, th = 0.9, 60.0
+    iota = th * math.pi / 180
+    m = orc.make_metric(a)
+    for al, be in [(-6.0, 4.0), (7.0, -3.0), (3.0, 9.0)]:
+        c = dict(r_obs=D, theta_obs=iota, nx=1, ny=1, alpha_min=al, alpha_max=al, beta_min=be, beta_max=be)
+        q0 = orc.initial_state(m, orc.make_camera(c), 0, 0)
+        ref = single_ray(orc, a, th, al, be, solver=W.solver(rtol=1e-10, atol=1e-12), disk=dict(r_out=20.0))
+        assert ref["hit_order"][0, 0] == 1  # first equatorial crossing lies on the disk
+        radii = []
+        for h_frac in (2e-3, 1e-3):
+            q, n = orc.rk4_run(m, q0, h_frac, 1.0, 2000.0, 10 ** 7, True)
+            h = h_frac * q[1]
+            lo, hi = 0.0, h
+            c0 = math.cos(q[2]) > 0
+            for _ in range(60):
+                mid = 0.5 * (lo + hi)
+                if (math.cos(orc.rk4_step(m, q, mid)[2]) > 0) == c0:
+                    lo = mid
+                else:
+                    hi = mid
+            radii.append(orc.rk4_step(m, q, 0.5 * (lo + hi))[1])
+        r_oracle = ref["hit_r"][0, 0]
+        # RK4 error ~ h^4: the finer run is ~16x closer; both bracket the oracle's value
+        assert abs(radii[1] - r_oracle) < abs(radii[0] - r_oracle) + 1e-12
+        assert radii[1] == pytest.approx(r_oracle, rel=1e-8)
+
+
+def test_approaching_side_brighter(orc):
+    a, th = 0.9, 60.0
+    c = W.camera(D, th, 24, 24, 15.0)
+    o = orc.trace(orc.make_metric(a), orc.make_camera(c), orc.make_disk(dict(r_out=20.0)),
+                  orc.make_solver(W.solver()))
+    I = o["intensity"].reshape(24, 24)
+    assert I[:, :12].sum() > 1.5 * I[:, 12:].sum()  # alpha < 0 is the approaching side
+    g1 = o["hit_g"][:, 0].reshape(24, 24)
+    assert g1[:, :12].max() > 1.0 > g1[:, 12:][g1[:, 12:] > 0].min()
+
+
+# ----------------------------------------------------------------- tabulated metric
+def poly_table(nr, nth, r_min, r_max):
+    u0, u1 = math.log(r_min), math.log(r_max)
+    us = u0 + (u1 - u0) * np.arange(nr) / (nr - 1)
+    ths = math.pi * np.arange(nth) / (nth - 1)
+    U, T = np.meshgrid(us, ths, indexing="ij")
+    pu = 1 + 0.3 * U - 0.05 * U ** 2 + 0.01 * U ** 3
+    dpu = 0.3 - 0.1 * U + 0.03 * U ** 2
+    pt = 2 - 0.4 * T + 0.2 * T ** 2 - 0.05 * T ** 3
+    dpt = -0.4 + 0.4 * T - 0.15 * T ** 2
+    r = np.exp(U)
+    tab = np.zeros((5, nr, nth, 4))
+    for cidx in range(5):
+        k = 1.0 + cidx
+        tab[cidx, :, :, 0] = k * pu * pt
+        tab[cidx, :, :, 1] = k * dpu * pt / r
+        tab[cidx, :, :, 2] = k * pu * dpt
+        tab[cidx, :, :, 3] = k * dpu * dpt / r
+    f = lambda u, t: (1 + 0.3 * u - 0.05 * u ** 2 + 0.01 * u ** 3) * (2 - 0.4 * t + 0.2 * t ** 2 - 0.05 * t ** 3)
+    return tab, f
+
+
+def test_table_interpolation_exact_on_bicubics(orc):
+    nr, nth, r_min, r_max = 17, 9, 2.0, 500.0
+    tab, f = poly_table(nr, nth, r_min, r_max)
+    m = orc.make_metric(0.5, tab, nr, nth, r_min, r_max)
+    rng = np.random.default_rng(5)
+    for _ in range(30):
+        r = math.exp(rng.uniform(math.log(r_min), math.log(r_max)))
+        th = rng.uniform(0.05, math.pi - 0.05)
+        g, gr, gt = orc.metric_eval(m, r, th)
+        u = math.log(r)
+        e = 1e-6
+        for cidx in (0, 2, 3):
+            k = 1.0 + cidx
+            assert g[cidx] == pytest.approx(k * f(u, th), rel=1e-12)
+            assert gr[cidx] == pytest.approx(k * (f(u + e, th) - f(u - e, th)) / (2 * e) / r, rel=1e-7)
+            assert gt[cidx] == pytest.approx(k * (f(u, th + e) - f(u, th - e)) / (2 * e), rel=1e-7)
+        assert g[1] == pytest.approx(2.0 * f(u, th) * math.sin(th) ** 2, rel=1e-12)
+
+
+def test_table_grid_refinement_fourth_order(orc):
+    a = 0.7
+    rp = orc.horizon(a)
+    r_min, r_max = 1.1 * rp, 2000.0
+    exact = orc.make_metric(a)
+    rng = np.random.default_rng(9)
+    pts = [(math.exp(rng.uniform(math.log(1.5 * rp), math.log(60.0))), rng.uniform(0.2, 2.9)) for _ in range(200)]
+    errs = []
+    for nr, nth in ((129, 65), (257, 129)):
+        tab = orc.build_kerr_table(a, nr, nth, r_min, r_max)
+        m = orc.make_metric(a, tab, nr, nth, r_min, r_max)
+        errs.append(np.array([np.abs(orc.metric_eval(m, r, th)[0] / orc.metric_eval(exact, r, th)[0] - 1)
+                              for r, th in pts]).max(axis=0))
+    ratio = errs[0] / errs[1]
+    assert np.all((ratio > 9) & (ratio < 25)), ratio  # bicubic Hermite: O(h^4) per component
+    # nodes reproduce the analytic metric exactly (up to rounding)
+    tab = orc.build_kerr_table(a, 65, 33, r_min, r_max)
+    m = orc.make_metric(a, tab, 65, 33, r_min, r_max)
+    u0, du = math.log(r_min), (math.log(r_max) - math.log(r_min)) / 64
+    r7 = math.exp(u0 + 7 * du)
+    th5 = 5 * math.pi / 32
+    g, gr, gt = orc.metric_eval(m, r7, th5)
+    gx, grx, gtx = orc.metric_eval(exact, r7, th5)
+    assert np.allclose(g, gx, rtol=1e-13) and np.allclose(gr, grx, rtol=1e-11) and np.allclose(gt, gtx, rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.slow
+def test_tabulated_trace_matches_analytic(orc):
+    a = 0.7
+    rp = orc.horizon(a)
+    nr, nth, r_min, r_max = 512, 256, 1.1 * rp, 2000.0
+    tab = orc.build_kerr_table(a, nr, nth, r_min, r_max)
+    c = W.camera(D, 40.0, 20, 20, 25.0)
+    disk = orc.make_disk(dict(r_out=20.0))
+    sv = orc.make_solver(W.solver())
+    ot = orc.trace(orc.make_metric(a, tab, nr, nth, r_min, r_max), orc.make_camera(c), disk, sv)
+    oa = orc.trace(orc.make_metric(a), orc.make_camera(c), disk, sv)
+    key_t = ot["cls"] * 10 + ot["n_hits"]
+    key_a = oa["cls"] * 10 + oa["n_hits"]
+    band = edge_band(key_a.reshape(20, 20)).ravel()
+    assert np.array_equal(key_t[~band], key_a[~band])
+    ok = (~band) & (key_t == key_a) & (oa["n_hits"] > 0)
+    rel = np.abs(ot["hit_r"][ok, 0] / oa["hit_r"][ok, 0] - 1)
+    assert rel.max() < 1e-5
