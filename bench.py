@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark of the Kerr null-geodesic tracer on one MI355X.
+
+Workload: Kerr a = 0.9, observer at r = 1000 M and 60 deg inclination, a
+512 x 512 camera over alpha, beta in [-25, 25] M, a Novikov-Thorne disk from
+r_ISCO to 20 M with up to 3 recorded crossings (synthetic camera grid, no
+data).  One "step" is one full trace of the image (camera initial conditions,
+Dormand-Prince 5(4) integration, events, shading) through the C ABI; inputs
+are generated on the device, so the timed region reads nothing from the host.
+
+The headline value is FP64 rays/s at the tolerance where the constraint gate
+|H| <= 1e-8 holds for every ray (rtol = 3e-10, atol = 3e-12; checked on the
+run's own outputs).  Extra legs report FP64 and mixed precision at rtol = 1e-8.
+The roofline entry prices the integrator kernel's algorithmic FP64 work
+(per-ray attempt counts x FLOPs per attempt) against the FP64 vector peak.
+The CPU baseline is the plain FP64 oracle on a seeded sample of the same
+image's pixels, on all host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/sec at |H|≤1e-8 (FP64 vs mixed, same GPU); p50/p99 image latency"
+GATE_RTOL, GATE_ATOL = 3e-10, 3e-12
+PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP32_TFLOPS = 78.6     # non-packed FP32 (packed FP32 is disabled in this build)
+
+# Algorithmic FLOPs (FMA = 2, division / sqrt / transcendental = 1) of the
+# analytic-Kerr FP64 path, counted from the formulas the kernel evaluates:
+FLOP_RHS = 72               # one right-hand side incl. H
+FLOP_ATTEMPT = 6 * FLOP_RHS + 140 + 66 + 72 + 38 + 5 + 6   # stages, y5, error, norm, controller, events = 759
+FLOP_RAY_INIT = 130         # observer metric, tetrad, first right-hand side
+FLOP_EVENT = 300            # Hermite set-up + ~40 bisection iterations
+FLOP_HIT = 120              # Omega, u^t, g, Page-Thorne flux
+
+
+def algorithmic_flops(out: dict) -> float:
+    att = out["n_accept"].astype(np.float64) + out["n_reject"]
+    return float(att.sum() * FLOP_ATTEMPT + len(att) * (FLOP_RAY_INIT + FLOP_EVENT)
+                 + out["n_cross"].sum() * FLOP_EVENT + out["n_hits"].sum() * FLOP_HIT)
+
+
+def time_leg(T, torch, args_tuple, out, steps, warmup):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        T.tartarus_trace(*args_tuple, out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        T.tartarus_trace(*args_tuple, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(w, solver, seconds: float) -> dict:
+    import oracle
+    oracle.build(force=False)
+    cam = w["cameras"][0]
+    n_img = cam["nx"] * cam["ny"]
+    m, c = oracle.make_metric(w["a"]), oracle.make_camera(cam)
+    d, s = oracle.make_disk(w["disk"]), oracle.make_solver(solver)
+    rng = np.random.default_rng(0)
+    probe = rng.choice(n_img, 1024, replace=False)
+    t = time.perf_counter()
+    oracle.trace(m, c, d, s, ray_ids=probe)
+    rate = 1024 / max(time.perf_counter() - t, 1e-6)
+    n = int(min(n_img, max(2048, rate * seconds)))
+    ids = rng.choice(n_img, n, replace=False)
+    t = time.perf_counter()
+    oracle.trace(m, c, d, s, ray_ids=ids)
+    dt = time.perf_counter() - t
+    return {"value": n / dt, "unit": "rays/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{n} seeded-random pixels of the same 512x512 image (rtol={solver['rtol']:g}), "
+                      f"plain FP64 C oracle, OpenMP over pixels, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="time only the headline leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the tracer shards by pixel rows or requests; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2609_08989_amd import tartarus as T
+
+    T.tartarus_init(0, 0)
+    w = W.WORKLOADS["kerr09_512"]
+    cam = w["cameras"][0]
+    n = cam["nx"] * cam["ny"]
+    metric, cams, disk = T.make_metric(w["a"]), [T.make_camera(cam)], T.make_disk(w["disk"])
+    gate_solver = dict(w["solver"], rtol=GATE_RTOL, atol=GATE_ATOL)
+    out = T.alloc_outputs(n)
+
+    # ---- headline: FP64 at the gate tolerance
+    leg_args = (metric, cams, disk, T.make_solver(gate_solver, T.PREC_FP64))
+    tuned = {}
+    if not args.no_autotune:
+        # untimed: pick the launch shape for this workload (part of the warm-up)
+        L = T.tartarus_autotune(*leg_args, out)
+        tuned["fp64"] = [L.block_threads, L.blocks_per_cu, L.chunk, L.refill_min]
+    wall, kern_ms = time_leg(T, torch, leg_args, out, args.steps, args.warmup)
+    o = T.to_numpy(out)
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * args.steps / wall
+    h_gate_max = float(o["h_gate"][o["cls"] != 2].max())
+    flops = algorithmic_flops(o)
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    att = o["n_accept"] + o["n_reject"]
+    result = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "kerr_a0.9_i60deg_r1000_512x512_disk_isco_to_20M", "rays": n,
+                   "rtol": GATE_RTOL, "atol": GATE_ATOL, "precision": "fp64",
+                   "gate_h_max": h_gate_max, "gate_holds": bool(h_gate_max <= 1e-8),
+                   "failed_rays": int((o["cls"] == 2).sum()), "attempts_per_ray": float(att.mean())},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "trace_persistent<0,0> (analytic Kerr, FP64)",
+                     "kernel_ms": kern_ms, "flop_per_launch": flops,
+                     "flop_per_attempt": FLOP_ATTEMPT},
+    }
+
+    # ---- extra legs at the config tolerance rtol = 1e-8
+    if not args.no_extra:
+        legs = {}
+        for name, prec in (("fp64_rtol1e-8", T.PREC_FP64), ("mixed_rtol1e-8", T.PREC_MIXED)):
+            la = (metric, cams, disk, T.make_solver(w["solver"], prec))
+            if prec == T.PREC_MIXED and not args.no_autotune:
+                L = T.tartarus_autotune(*la, out)
+                tuned["mixed"] = [L.block_threads, L.blocks_per_cu, L.chunk, L.refill_min]
+            wl, km = time_leg(T, torch, la, out, args.steps, args.warmup)
+            ol = T.to_numpy(out)
+            attl = ol["n_accept"] + ol["n_reject"]
+            legs[name] = {"rays_per_s": n * args.steps / wl, "kernel_ms": km,
+                          "attempts_per_ray": float(attl.mean()),
+                          "fp32_attempt_frac": float(ol["n_fp32"].sum() / attl.sum()),
+                          "gate_frac_le_1e-8": float(np.mean(ol["h_gate"] <= 1e-8)),
+                          "failed_rays": int((ol["cls"] == 2).sum())}
+        legs["mixed_over_fp64_same_rtol"] = legs["mixed_rtol1e-8"]["rays_per_s"] / legs["fp64_rtol1e-8"]["rays_per_s"]
+        legs["mixed_rtol1e-8_over_fp64_gate"] = legs["mixed_rtol1e-8"]["rays_per_s"] / value
+        result["legs"] = legs
+
+    if tuned:
+        result["launch_shape"] = {k: dict(zip(("block_threads", "blocks_per_cu", "chunk", "refill_min"), v))
+                                  for k, v in tuned.items()}
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w, gate_solver, args.cpu_seconds)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,88 @@
+// internal.hpp -- structures shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace tartarus {
+
+// One camera (trace) or one image request (serving): a contiguous range of
+// global ray indices with its own parameters and output pointers (already
+// offset to the job's first ray).
+struct DevJob {
+    long long ray_begin;
+    long long ray_count;
+    int nx, ny;
+    int max_hits;
+    int pad0;
+    double a;
+    double r_obs, theta_obs;
+    double alpha_min, alpha_max, beta_min, beta_max;
+    double disk_r_in, disk_r_out;   // r_in <= 0: prograde ISCO
+    int32_t* cls;
+    int32_t* n_hits;
+    double* final_rtp;
+    double* h_drift;
+    double* h_gate;
+    double* hit_r;
+    double* hit_g;
+    double* hit_flux;
+    double* hit_lambda;
+    int32_t* hit_order;
+    double* intensity;
+    int32_t* n_accept;
+    int32_t* n_reject;
+    int32_t* n_fp32;
+    int32_t* n_cross;
+    unsigned int* remaining;        // serving: rays still running (may be null)
+    int cancelled;                  // serving: drop the job's rays without writing outputs
+    int pad1;
+};
+
+// Per-job constants computed on the device by the set-up kernel before a
+// trace: the observer's metric and ZAMO tetrad (Sec. 2.2), the horizon
+// radius, the disk's inner edge and the Page-Thorne roots and coefficients
+// (Sec. 2.3).
+struct JobConst {
+    double g[5];                    // covariant metric at the observer
+    double ett, etp, err, ehh, epp; // tetrad components e_(t)^t, e_(t)^phi, e_(r)^r, e_(th)^th, e_(ph)^ph
+    double c2_obs, is2_obs;         // cos^2 and 1 / sin^2 of the inclination
+    double rp;                      // horizon radius r_+
+    double r_in, x0;                // disk inner edge (r_ISCO if not given) and sqrt(r_in)
+    double xi[3], coef[3];          // roots of x^3 - 3x + 2a and their Page-Thorne coefficients
+};
+
+// Per-launch uniform parameters.
+struct LaunchArgs {
+    const DevJob* jobs;
+    const JobConst* jc;
+    int njobs;
+    int chunk;                      // ray ids fetched per wavefront
+    int refill_min;                 // idle lanes that trigger a refill
+    int pad0;
+    long long total_rays;           // global ray indices run over [first_ray, total_rays)
+    long long first_ray;
+    unsigned long long* head;       // global queue head (relative to first_ray)
+    double rtol, atol, h0_frac, event_tol;
+    double horizon_factor, r_escape;
+    long long max_steps;
+    // tabulated metric (kind 1)
+    const double* table;
+    int nr, nth;
+    double tab_r_min, tab_r_max;
+    // mixed precision regime thresholds
+    double r_switch_factor;         // FP32 stages only where r >= factor * r_+
+    double turn_r, turn_th;         // turning-point guards (fractions)
+    // serving epochs: resume / park ray state (null for one-shot traces)
+    double* slots;                  // [nslot][SLOT_DOUBLES] parked state, slot = global lane id
+    long long step_budget;          // attempts per lane per launch before parking (<= 0: none)
+    unsigned int* slot_live;        // [nslot] 1 if a parked ray lives in the slot
+    // serving: directory from global ray index to job-table entry, sorted by begin
+    const long long* dir_begin;     // null: look up jobs[].ray_begin directly
+    const int* dir_job;
+    int ndir;
+    int pad2;
+};
+
+constexpr int SLOT_DOUBLES = 32;
+
+}  // namespace tartarus

@@ -1,0 +1,963 @@
+// runtime.cpp -- host side of the C ABI declared in include/tartarus.h.
+//
+// The host validates arguments, copies them into a device job table (one entry
+// per camera or request) and launches the persistent integrator; it performs
+// none of the ray arithmetic.  Serving (submit / poll) runs a scheduler thread
+// that admits requests by HBM budget and traces them together in epochs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/tartarus.h"
+#include "internal.hpp"
+
+using namespace tartarus;
+
+extern "C" hipError_t tartarus_launch_trace(int kind, int prec, const LaunchArgs* args, int grid, int block,
+                                            hipStream_t stream);
+extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hipStream_t stream);
+extern "C" hipError_t tartarus_launch_shade(const LaunchArgs* args, int job0, int njobs, long long max_rays,
+                                            hipStream_t stream);
+extern "C" hipError_t tartarus_occupancy(int kind, int prec, int block, int* blocks_per_cu);
+extern "C" hipError_t tartarus_launch_build_table(double a, int nr, int nth, double r_min, double r_max,
+                                                  double* table, hipStream_t stream);
+extern "C" hipError_t tartarus_launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t stream);
+extern "C" hipError_t tartarus_launch_fill_u64(unsigned long long* p, unsigned long long v, long long n,
+                                               hipStream_t stream);
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(TARTARUS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+    } while (0)
+
+// Default mixed-precision regime: FP32 stages where r >= 10 r_+, away from
+// radial (|p_r| < 0.05 |p_t|) and polar (|p_theta| < 0.05 sqrt(Q)) turning points.
+constexpr double kDefaultSwitch = 10.0;
+constexpr double kDefaultTurnR = 0.05;
+constexpr double kDefaultTurnTh = 0.05;
+
+// Per-call launch resources.  A trace copies its job table through pinned host
+// memory into a device table and resets a queue head, then launches; the slot
+// is reused only after the event recorded behind that launch has completed, so
+// calls stay asynchronous without a host buffer outliving its copy.
+struct Slot {
+    DevJob* djobs = nullptr;
+    DevJob* hjobs = nullptr;             // pinned
+    JobConst* djc = nullptr;             // per-job constants (device, written by the set-up kernel)
+    int cap = 0;
+    unsigned long long* head = nullptr;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+constexpr int kSlots = 16;
+
+struct Device {
+    bool ready = false;
+    int id = 0;
+    int cus = 0;
+    size_t budget = 0;
+    std::mutex mu;                       // guards the slots and the tuning table
+    Slot slots[kSlots];
+    int next_slot = 0;
+    std::map<int, tartarus_launch> tuned;  // key: kind * 2 + precision
+};
+Device g_dev;
+
+int take_slot(int njobs, Slot*& out)
+{
+    Slot& S = g_dev.slots[g_dev.next_slot];
+    g_dev.next_slot = (g_dev.next_slot + 1) % kSlots;
+    if (S.pending) {
+        HIP_TRY(hipEventSynchronize(S.ev));
+        S.pending = false;
+    }
+    if (!S.ev) HIP_TRY(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
+    if (!S.head) HIP_TRY(hipMalloc(&S.head, sizeof(unsigned long long)));
+    if (njobs > S.cap) {
+        if (S.djobs) (void)hipFree(S.djobs);
+        if (S.hjobs) (void)hipHostFree(S.hjobs);
+        if (S.djc) (void)hipFree(S.djc);
+        S.djobs = nullptr;
+        S.hjobs = nullptr;
+        S.djc = nullptr;
+        S.cap = 0;
+        const int cap = std::max(njobs, 64);
+        if (hipMalloc(&S.djobs, sizeof(DevJob) * cap) != hipSuccess) return fail(TARTARUS_E_NOMEM, "job table allocation failed");
+        if (hipMalloc(&S.djc, sizeof(JobConst) * cap) != hipSuccess) return fail(TARTARUS_E_NOMEM, "job constants allocation failed");
+        if (hipHostMalloc(&S.hjobs, sizeof(DevJob) * cap, hipHostMallocDefault) != hipSuccess)
+            return fail(TARTARUS_E_NOMEM, "pinned job table allocation failed");
+        S.cap = cap;
+    }
+    out = &S;
+    return TARTARUS_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_metric(const tartarus_metric* m, int precision)
+{
+    if (!m) return fail(TARTARUS_E_INVALID, "metric is NULL");
+    if (!(std::isfinite(m->a) && m->a >= 0.0 && m->a < 1.0)) return fail(TARTARUS_E_INVALID, "spin a must be in [0, 1)");
+    if (m->kind == TARTARUS_METRIC_TABLE) {
+        if (!m->table) return fail(TARTARUS_E_INVALID, "tabulated metric needs a table");
+        if (m->nr < 4 || m->nth < 4) return fail(TARTARUS_E_INVALID, "table needs nr, nth >= 4");
+        if (!finite_pos(m->r_min) || !(m->r_max > m->r_min) || !std::isfinite(m->r_max))
+            return fail(TARTARUS_E_INVALID, "table needs 0 < r_min < r_max");
+        if (precision != TARTARUS_PREC_FP64)
+            return fail(TARTARUS_E_INVALID, "the tabulated metric is traced in FP64 only");
+    } else if (m->kind != TARTARUS_METRIC_KERR) {
+        return fail(TARTARUS_E_INVALID, "unknown metric kind");
+    }
+    return TARTARUS_OK;
+}
+
+int check_camera(const tartarus_camera& c, const tartarus_solver* s)
+{
+    if (!finite_pos(c.r_obs)) return fail(TARTARUS_E_INVALID, "r_obs must be > 0");
+    if (!(std::isfinite(c.theta_obs) && c.theta_obs > 0.0 && c.theta_obs < M_PI))
+        return fail(TARTARUS_E_INVALID, "theta_obs must be in (0, pi)");
+    if (c.nx < 1 || c.ny < 1) return fail(TARTARUS_E_INVALID, "nx, ny must be >= 1");
+    const double w[4] = {c.alpha_min, c.alpha_max, c.beta_min, c.beta_max};
+    for (double v : w)
+        if (!std::isfinite(v)) return fail(TARTARUS_E_INVALID, "non-finite image window");
+    const double am = std::max(std::fabs(c.alpha_min), std::fabs(c.alpha_max));
+    const double bm = std::max(std::fabs(c.beta_min), std::fabs(c.beta_max));
+    if (!(am * am + bm * bm < c.r_obs * c.r_obs)) return fail(TARTARUS_E_INVALID, "image window must satisfy alpha^2 + beta^2 < r_obs^2");
+    if (s && !(s->r_escape > c.r_obs)) return fail(TARTARUS_E_INVALID, "r_escape must exceed r_obs");
+    if ((long long)c.nx * c.ny > (1ll << 40)) return fail(TARTARUS_E_INVALID, "image too large");
+    return TARTARUS_OK;
+}
+
+int check_solver(const tartarus_solver* s)
+{
+    if (!s) return fail(TARTARUS_E_INVALID, "solver is NULL");
+    if (!finite_pos(s->rtol)) return fail(TARTARUS_E_INVALID, "rtol must be > 0");
+    if (!finite_pos(s->atol)) return fail(TARTARUS_E_INVALID, "atol must be > 0");
+    if (!finite_pos(s->h0_frac)) return fail(TARTARUS_E_INVALID, "h0_frac must be > 0");
+    if (!(std::isfinite(s->horizon_factor) && s->horizon_factor >= 1.0))
+        return fail(TARTARUS_E_INVALID, "horizon_factor must be >= 1");
+    if (!finite_pos(s->r_escape)) return fail(TARTARUS_E_INVALID, "r_escape must be > 0");
+    if (!finite_pos(s->event_tol)) return fail(TARTARUS_E_INVALID, "event_tol must be > 0");
+    if (s->max_steps < 1) return fail(TARTARUS_E_INVALID, "max_steps must be >= 1");
+    if (s->precision != TARTARUS_PREC_FP64 && s->precision != TARTARUS_PREC_MIXED)
+        return fail(TARTARUS_E_INVALID, "unknown precision");
+    if (s->method != 0) return fail(TARTARUS_E_INVALID, "only method 0 (Dormand-Prince 5(4)) is provided");
+    return TARTARUS_OK;
+}
+
+int check_disk(const tartarus_disk* d)
+{
+    if (!d) return fail(TARTARUS_E_INVALID, "disk is NULL");
+    if (d->max_hits < 0 || d->max_hits > 3) return fail(TARTARUS_E_INVALID, "max_hits must be in 0..3");
+    if (d->max_hits > 0) {
+        if (!std::isfinite(d->r_in) || !std::isfinite(d->r_out)) return fail(TARTARUS_E_INVALID, "non-finite disk radii");
+        if (!(d->r_out > 0.0)) return fail(TARTARUS_E_INVALID, "disk r_out must be > 0");
+        if (d->r_in > 0.0 && !(d->r_out > d->r_in)) return fail(TARTARUS_E_INVALID, "disk needs r_out > r_in");
+    }
+    return TARTARUS_OK;
+}
+
+int check_outputs(const tartarus_outputs* o)
+{
+    if (!o) return fail(TARTARUS_E_INVALID, "outputs is NULL");
+    const void* p[] = {o->cls, o->n_hits, o->final_rtp, o->h_drift, o->h_gate, o->hit_r, o->hit_g, o->hit_flux,
+                       o->hit_lambda, o->hit_order, o->intensity, o->n_accept, o->n_reject, o->n_fp32, o->n_cross};
+    for (const void* q : p)
+        if (!q) return fail(TARTARUS_E_INVALID, "an output buffer is NULL");
+    return TARTARUS_OK;
+}
+
+int validate_all(const tartarus_metric* metric, const tartarus_camera* cams, int ncams, const tartarus_disk* disk,
+                 const tartarus_solver* solver)
+{
+    int rc;
+    if ((rc = check_solver(solver))) return rc;
+    if ((rc = check_metric(metric, solver->precision))) return rc;
+    if ((rc = check_disk(disk))) return rc;
+    if (!cams || ncams < 1) return fail(TARTARUS_E_INVALID, "need at least one camera");
+    for (int c = 0; c < ncams; ++c) {
+        if ((rc = check_camera(cams[c], solver))) return rc;
+        if (cams[c].nx != cams[0].nx || cams[c].ny != cams[0].ny)
+            return fail(TARTARUS_E_INVALID, "all cameras of a trace must share nx, ny");
+    }
+    return TARTARUS_OK;
+}
+
+void fill_job(DevJob& J, const tartarus_metric* m, const tartarus_camera& c, const tartarus_disk* d,
+              const tartarus_solver* s, const tartarus_outputs* o, long long begin, long long offset)
+{
+    std::memset(&J, 0, sizeof(J));
+    J.ray_begin = begin;
+    J.ray_count = (long long)c.nx * c.ny;
+    J.nx = c.nx;
+    J.ny = c.ny;
+    J.max_hits = d->max_hits;
+    J.a = m->a;
+    J.r_obs = c.r_obs;
+    J.theta_obs = c.theta_obs;
+    J.alpha_min = c.alpha_min;
+    J.alpha_max = c.alpha_max;
+    J.beta_min = c.beta_min;
+    J.beta_max = c.beta_max;
+    J.disk_r_in = d->r_in;
+    J.disk_r_out = d->r_out;
+    J.cls = o->cls + offset;
+    J.n_hits = o->n_hits + offset;
+    J.final_rtp = o->final_rtp + 3 * offset;
+    J.h_drift = o->h_drift + offset;
+    J.h_gate = o->h_gate + offset;
+    J.hit_r = o->hit_r + 3 * offset;
+    J.hit_g = o->hit_g + 3 * offset;
+    J.hit_flux = o->hit_flux + 3 * offset;
+    J.hit_lambda = o->hit_lambda + 3 * offset;
+    J.hit_order = o->hit_order + 3 * offset;
+    J.intensity = o->intensity + offset;
+    J.n_accept = o->n_accept + offset;
+    J.n_reject = o->n_reject + offset;
+    J.n_fp32 = o->n_fp32 + offset;
+    J.n_cross = o->n_cross + offset;
+    J.remaining = nullptr;
+}
+
+void fill_args(LaunchArgs& A, const tartarus_metric* m, const tartarus_solver* s)
+{
+    std::memset(&A, 0, sizeof(A));
+    A.rtol = s->rtol;
+    A.atol = s->atol;
+    A.h0_frac = s->h0_frac;
+    A.event_tol = s->event_tol;
+    A.horizon_factor = s->horizon_factor;
+    A.r_escape = s->r_escape;
+    A.max_steps = s->max_steps;
+    A.r_switch_factor = kDefaultSwitch;
+    A.turn_r = kDefaultTurnR;
+    A.turn_th = kDefaultTurnTh;
+    // experiment overrides of the mixed-precision regime
+    if (const char* e = std::getenv("TARTARUS_MIXED_SWITCH")) {
+        const double v = std::atof(e);
+        if (v > 0.0) A.r_switch_factor = v;
+    }
+    if (const char* e = std::getenv("TARTARUS_MIXED_TURN_R")) A.turn_r = std::atof(e);
+    if (const char* e = std::getenv("TARTARUS_MIXED_TURN_TH")) A.turn_th = std::atof(e);
+    if (m->kind == TARTARUS_METRIC_TABLE) {
+        A.table = m->table;
+        A.nr = m->nr;
+        A.nth = m->nth;
+        A.tab_r_min = m->r_min;
+        A.tab_r_max = m->r_max;
+    }
+}
+
+tartarus_launch default_launch(int kind, int prec)
+{
+    auto it = g_dev.tuned.find(kind * 2 + prec);
+    if (it != g_dev.tuned.end()) return it->second;
+    tartarus_launch L;
+    L.block_threads = 256;
+    L.blocks_per_cu = 0;
+    L.chunk = 64;
+    L.refill_min = 4;
+    return L;
+}
+
+int resolve_launch(int kind, int prec, const tartarus_launch* req, tartarus_launch& L, int& grid)
+{
+    L = default_launch(kind, prec);
+    if (req) {
+        if (req->block_threads > 0) L.block_threads = req->block_threads;
+        if (req->blocks_per_cu > 0) L.blocks_per_cu = req->blocks_per_cu;
+        if (req->chunk > 0) L.chunk = req->chunk;
+        if (req->refill_min > 0) L.refill_min = req->refill_min;
+    }
+    if (L.block_threads != 64 && L.block_threads != 128 && L.block_threads != 256)
+        return fail(TARTARUS_E_INVALID, "block_threads must be 64, 128 or 256");
+    if (L.refill_min < 1 || L.refill_min > 64) return fail(TARTARUS_E_INVALID, "refill_min must be in 1..64");
+    if (L.chunk < 1) return fail(TARTARUS_E_INVALID, "chunk must be >= 1");
+    int occ = 0;
+    HIP_TRY(tartarus_occupancy(kind, prec, L.block_threads, &occ));
+    if (occ < 1) return fail(TARTARUS_E_DEVICE, "kernel cannot be resident with this block size");
+    if (L.blocks_per_cu <= 0 || L.blocks_per_cu > occ) L.blocks_per_cu = occ;
+    grid = g_dev.cus * L.blocks_per_cu;
+    return TARTARUS_OK;
+}
+
+// Enqueue one trace (no validation) on the stream.
+int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, int ncams, const tartarus_disk* disk,
+                  const tartarus_solver* solver, const tartarus_outputs* out, const tartarus_launch* launch,
+                  hipStream_t stream)
+{
+    const int kind = metric->kind, prec = solver->precision;
+    tartarus_launch L;
+    int grid = 0;
+    int rc = resolve_launch(kind, prec, launch, L, grid);
+    if (rc) return rc;
+    Slot* S = nullptr;
+    if ((rc = take_slot(ncams, S))) return rc;
+    const long long per = (long long)cams[0].nx * cams[0].ny;
+    for (int c = 0; c < ncams; ++c) fill_job(S->hjobs[c], metric, cams[c], disk, solver, out, c * per, c * per);
+    HIP_TRY(hipMemcpyAsync(S->djobs, S->hjobs, sizeof(DevJob) * ncams, hipMemcpyHostToDevice, stream));
+    HIP_TRY(tartarus_launch_fill_u64(S->head, 0ull, 1, stream));
+    LaunchArgs A;
+    fill_args(A, metric, solver);
+    A.jobs = S->djobs;
+    A.jc = S->djc;
+    A.njobs = ncams;
+    A.chunk = L.chunk;
+    A.refill_min = L.refill_min;
+    A.first_ray = 0;
+    A.total_rays = per * ncams;
+    A.head = S->head;
+    HIP_TRY(tartarus_launch_setup(kind, &A, stream));
+    HIP_TRY(tartarus_launch_trace(kind, prec, &A, grid, L.block_threads, stream));
+    for (int c0 = 0; c0 < ncams; c0 += 65535)
+        HIP_TRY(tartarus_launch_shade(&A, c0, std::min(65535, ncams - c0), per, stream));
+    HIP_TRY(hipEventRecord(S->ev, stream));
+    S->pending = true;
+    return TARTARUS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported
+// ---------------------------------------------------------------------------
+extern "C" const char* tartarus_last_error(void) { return g_err.c_str(); }
+
+extern "C" int tartarus_validate(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
+                                 const tartarus_disk* disk, const tartarus_solver* solver)
+{
+    return validate_all(metric, cams, ncams, disk, solver);
+}
+
+extern "C" int tartarus_init(int device, size_t hbm_budget_bytes)
+{
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(TARTARUS_E_DEVICE, "no HIP device");
+    if (device < 0 || device >= n) return fail(TARTARUS_E_INVALID, "device index out of range");
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(TARTARUS_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950");
+    if (g_dev.ready && g_dev.id == device) {
+        g_dev.budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)8 << 30;
+        return TARTARUS_OK;
+    }
+    g_dev.id = device;
+    g_dev.cus = prop.multiProcessorCount;
+    g_dev.budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)8 << 30;
+    g_dev.ready = true;
+    return TARTARUS_OK;
+}
+
+extern "C" int tartarus_trace_launch(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
+                                     const tartarus_disk* disk, const tartarus_solver* solver,
+                                     const tartarus_outputs* out, const tartarus_launch* launch, void* hip_stream)
+{
+    int rc = validate_all(metric, cams, ncams, disk, solver);
+    if (rc) return rc;
+    if ((rc = check_outputs(out))) return rc;
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    HIP_TRY(hipSetDevice(g_dev.id));
+    return enqueue_trace(metric, cams, ncams, disk, solver, out, launch, (hipStream_t)hip_stream);
+}
+
+extern "C" int tartarus_trace(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
+                              const tartarus_disk* disk, const tartarus_solver* solver, const tartarus_outputs* out,
+                              void* hip_stream)
+{
+    return tartarus_trace_launch(metric, cams, ncams, disk, solver, out, nullptr, hip_stream);
+}
+
+extern "C" int tartarus_build_kerr_table(double a, int nr, int nth, double r_min, double r_max, double* table,
+                                         void* hip_stream)
+{
+    if (!(std::isfinite(a) && a >= 0.0 && a < 1.0)) return fail(TARTARUS_E_INVALID, "spin a must be in [0, 1)");
+    if (nr < 4 || nth < 4) return fail(TARTARUS_E_INVALID, "table needs nr, nth >= 4");
+    if (!finite_pos(r_min) || !(r_max > r_min) || !std::isfinite(r_max))
+        return fail(TARTARUS_E_INVALID, "table needs 0 < r_min < r_max");
+    if (!table) return fail(TARTARUS_E_INVALID, "table is NULL");
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    HIP_TRY(hipSetDevice(g_dev.id));
+    HIP_TRY(tartarus_launch_build_table(a, nr, nth, r_min, r_max, table, (hipStream_t)hip_stream));
+    return TARTARUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: coordinate search over the launch shape on the caller's workload
+// ---------------------------------------------------------------------------
+namespace {
+
+int time_trace(const tartarus_metric* metric, const tartarus_camera* cams, int ncams, const tartarus_disk* disk,
+               const tartarus_solver* solver, const tartarus_outputs* out, const tartarus_launch& L,
+               hipStream_t stream, float& ms)
+{
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, stream));
+    int rc = enqueue_trace(metric, cams, ncams, disk, solver, out, &L, stream);
+    if (rc) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
+    }
+    HIP_TRY(hipEventRecord(e1, stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return TARTARUS_OK;
+}
+
+}  // namespace
+
+extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
+                                 const tartarus_disk* disk, const tartarus_solver* solver,
+                                 const tartarus_outputs* out, void* hip_stream, tartarus_launch* best)
+{
+    int rc = validate_all(metric, cams, ncams, disk, solver);
+    if (rc) return rc;
+    if ((rc = check_outputs(out))) return rc;
+    if (!best) return fail(TARTARUS_E_INVALID, "best is NULL");
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    HIP_TRY(hipSetDevice(g_dev.id));
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const int kind = metric->kind, prec = solver->precision;
+    g_dev.tuned.erase(kind * 2 + prec);
+    tartarus_launch cur = default_launch(kind, prec);
+    int grid = 0;
+    if ((rc = resolve_launch(kind, prec, &cur, cur, grid))) return rc;
+    float best_ms = 0.f;
+    if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;  // warm-up
+    if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;
+    const int blocks[] = {64, 128, 256};
+    const int chunks[] = {64, 256, 1024, 4096};
+    const int refills[] = {1, 8, 16, 32, 48};
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int b : blocks) {
+            tartarus_launch L = cur;
+            L.block_threads = b;
+            L.blocks_per_cu = 0;
+            int g2 = 0;
+            if (resolve_launch(kind, prec, &L, L, g2)) continue;
+            float ms = 0.f;
+            if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; cur = L; }
+        }
+        int occ = 0;
+        HIP_TRY(tartarus_occupancy(kind, prec, cur.block_threads, &occ));
+        for (int bpc = 1; bpc <= occ; ++bpc) {
+            tartarus_launch L = cur;
+            L.blocks_per_cu = bpc;
+            float ms = 0.f;
+            if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; cur = L; }
+        }
+        for (int c : chunks) {
+            tartarus_launch L = cur;
+            L.chunk = c;
+            float ms = 0.f;
+            if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; cur = L; }
+        }
+        for (int f : refills) {
+            tartarus_launch L = cur;
+            L.refill_min = f;
+            float ms = 0.f;
+            if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; cur = L; }
+        }
+    }
+    g_dev.tuned[kind * 2 + prec] = cur;
+    *best = cur;
+    return TARTARUS_OK;
+}
+
+namespace {
+void server_stop();
+}
+
+extern "C" int tartarus_shutdown(void)
+{
+    server_stop();
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    if (!g_dev.ready) return TARTARUS_OK;
+    (void)hipSetDevice(g_dev.id);
+    for (Slot& S : g_dev.slots) {
+        if (S.pending) (void)hipEventSynchronize(S.ev);
+        if (S.djobs) (void)hipFree(S.djobs);
+        if (S.hjobs) (void)hipHostFree(S.hjobs);
+        if (S.djc) (void)hipFree(S.djc);
+        if (S.head) (void)hipFree(S.head);
+        if (S.ev) (void)hipEventDestroy(S.ev);
+        S = Slot();
+    }
+    g_dev.tuned.clear();
+    g_dev.ready = false;
+    return TARTARUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching of image requests
+//
+// Requests are admitted in arrival order while their output bytes plus the
+// ray-slot arena fit the HBM budget (and a request-table entry is free).  All
+// admitted requests share one device queue of global ray indices; the
+// persistent kernel runs in epochs of a bounded number of attempts per lane,
+// parks unfinished rays in their lane's slot (exact bits) and resumes them in
+// the next epoch, so requests that arrive while others are on the device join
+// at the next epoch boundary and their rays overlap with the running ones.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kMaxEntries = 256;        // request-table entries (requests in flight)
+constexpr long long kEpochAttempts = 192;  // attempts per lane per epoch
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+size_t output_bytes_per_ray()
+{
+    // cls, n_hits, n_accept, n_reject, n_fp32, n_cross (int32); final_rtp[3], h_drift,
+    // h_gate, intensity (double); hit_r, hit_g, hit_flux, hit_lambda [3] (double); hit_order[3] (int32)
+    return 6 * 4 + 6 * 8 + 12 * 8 + 3 * 4;
+}
+
+struct Request {
+    tartarus_metric metric;
+    tartarus_camera cam;
+    tartarus_disk disk;
+    tartarus_solver solver;
+    tartarus_outputs out;
+    long long nrays = 0;
+    size_t bytes = 0;
+    int state = 0;          // 0 queued, 1 running, 2 done
+    int entry = -1;
+    long long ray_begin = 0;
+    int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    bool cancel_req = false, cancel_sent = false, cancel_acked = false;
+};
+
+struct Server {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;       // wakes the scheduler
+    std::condition_variable done_cv;  // wakes waiters
+    bool running = false;
+    bool have_solver = false;
+    tartarus_solver solver;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, Request> reqs;
+    uint64_t next_ticket = 1;
+    uint64_t entry_ticket[kMaxEntries] = {};
+    size_t used_bytes = 0;
+    long long next_ray = 0;    // global ray indices handed out so far
+    long long first_ray = 0;   // rays before this index were taken from the queue
+    // device resources (owned by the scheduler thread once started)
+    bool dev_ready = false;
+    hipStream_t stream = nullptr;
+    DevJob* djobs = nullptr;
+    DevJob* hjobs = nullptr;
+    JobConst* djc = nullptr;
+    unsigned int* dremaining = nullptr;
+    unsigned int* hremaining = nullptr;
+    long long* ddir_begin = nullptr;
+    int* ddir_job = nullptr;
+    long long* hdir_begin = nullptr;
+    int* hdir_job = nullptr;
+    double* slots = nullptr;
+    unsigned int* slot_live = nullptr;
+    unsigned long long* dhead = nullptr;
+    unsigned long long* hhead = nullptr;
+    long long nslots = 0;
+    int grid = 0, block = 0;
+    size_t arena_bytes = 0;
+    std::string dev_error;
+};
+Server g_srv;
+
+int server_alloc(int prec)
+{
+    Server& S = g_srv;
+    HIP_TRY(hipSetDevice(g_dev.id));
+    HIP_TRY(hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
+    tartarus_launch L;
+    int grid = 0;
+    int rc = resolve_launch(TARTARUS_METRIC_KERR, prec, nullptr, L, grid);
+    if (rc) return rc;
+    S.grid = grid;
+    S.block = L.block_threads;
+    S.nslots = (long long)grid * L.block_threads;
+    HIP_TRY(hipMalloc(&S.djobs, sizeof(DevJob) * kMaxEntries));
+    HIP_TRY(hipMalloc(&S.djc, sizeof(JobConst) * kMaxEntries));
+    HIP_TRY(hipHostMalloc(&S.hjobs, sizeof(DevJob) * kMaxEntries, hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&S.dremaining, sizeof(unsigned int) * kMaxEntries));
+    HIP_TRY(hipHostMalloc(&S.hremaining, sizeof(unsigned int) * kMaxEntries, hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&S.ddir_begin, sizeof(long long) * kMaxEntries));
+    HIP_TRY(hipMalloc(&S.ddir_job, sizeof(int) * kMaxEntries));
+    HIP_TRY(hipHostMalloc(&S.hdir_begin, sizeof(long long) * kMaxEntries, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&S.hdir_job, sizeof(int) * kMaxEntries, hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&S.slots, sizeof(double) * SLOT_DOUBLES * S.nslots));
+    HIP_TRY(hipMalloc(&S.slot_live, sizeof(unsigned int) * S.nslots));
+    HIP_TRY(hipMalloc(&S.dhead, sizeof(unsigned long long)));
+    HIP_TRY(hipHostMalloc(&S.hhead, sizeof(unsigned long long), hipHostMallocDefault));
+    HIP_TRY(tartarus_launch_fill_u32(S.slot_live, 0u, S.nslots, S.stream));
+    HIP_TRY(tartarus_launch_fill_u32(S.dremaining, 0u, kMaxEntries, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    std::memset(S.hjobs, 0, sizeof(DevJob) * kMaxEntries);
+    S.arena_bytes = sizeof(double) * SLOT_DOUBLES * S.nslots + sizeof(unsigned int) * S.nslots +
+                    (sizeof(DevJob) + 16) * kMaxEntries;
+    S.dev_ready = true;
+    return TARTARUS_OK;
+}
+
+void server_free()
+{
+    Server& S = g_srv;
+    if (S.stream) (void)hipStreamSynchronize(S.stream);
+    (void)hipFree(S.djobs);
+    (void)hipFree(S.djc);
+    (void)hipHostFree(S.hjobs);
+    (void)hipFree(S.dremaining);
+    (void)hipHostFree(S.hremaining);
+    (void)hipFree(S.ddir_begin);
+    (void)hipFree(S.ddir_job);
+    (void)hipHostFree(S.hdir_begin);
+    (void)hipHostFree(S.hdir_job);
+    (void)hipFree(S.slots);
+    (void)hipFree(S.slot_live);
+    (void)hipFree(S.dhead);
+    (void)hipHostFree(S.hhead);
+    if (S.stream) (void)hipStreamDestroy(S.stream);
+    S.djobs = nullptr; S.djc = nullptr; S.hjobs = nullptr; S.dremaining = nullptr; S.hremaining = nullptr;
+    S.ddir_begin = nullptr; S.ddir_job = nullptr; S.hdir_begin = nullptr; S.hdir_job = nullptr;
+    S.slots = nullptr; S.slot_live = nullptr; S.dhead = nullptr; S.hhead = nullptr; S.stream = nullptr;
+    S.dev_ready = false;
+}
+
+bool any_live(const Server& S)
+{
+    for (int e = 0; e < kMaxEntries; ++e)
+        if (S.entry_ticket[e]) return true;
+    return false;
+}
+
+void finish_request(Server& S, uint64_t ticket, Request& R)
+{
+    R.state = 2;
+    R.t_done = now_ns();
+    if (R.entry >= 0) {
+        S.entry_ticket[R.entry] = 0;
+        S.hjobs[R.entry].cancelled = 0;
+        R.entry = -1;
+        S.used_bytes -= R.bytes;
+    }
+    (void)ticket;
+}
+
+// One scheduling round: admit, run one epoch, collect completions.
+int server_round(std::unique_lock<std::mutex>& lk)
+{
+    Server& S = g_srv;
+    // ---- admission (arrival order; head-of-line blocking keeps it FIFO)
+    std::vector<int> fresh;
+    while (!S.queue.empty()) {
+        const uint64_t t = S.queue.front();
+        Request& R = S.reqs[t];
+        int entry = -1;
+        for (int e = 0; e < kMaxEntries; ++e)
+            if (!S.entry_ticket[e]) { entry = e; break; }
+        if (entry < 0 || S.used_bytes + R.bytes + S.arena_bytes > g_dev.budget) break;
+        S.queue.pop_front();
+        R.entry = entry;
+        R.ray_begin = S.next_ray;
+        S.next_ray += R.nrays;
+        S.used_bytes += R.bytes;
+        R.state = 1;
+        R.t_admit = now_ns();
+        S.entry_ticket[entry] = t;
+        fill_job(S.hjobs[entry], &R.metric, R.cam, &R.disk, &R.solver, &R.out, R.ray_begin, 0);
+        S.hjobs[entry].remaining = S.dremaining + entry;
+        S.hjobs[entry].cancelled = 0;
+        S.hremaining[entry] = (unsigned int)R.nrays;
+        fresh.push_back(entry);
+    }
+    // ---- cancellations become visible to the kernel from this epoch on
+    std::vector<uint64_t> sent;
+    for (int e = 0; e < kMaxEntries; ++e) {
+        const uint64_t t = S.entry_ticket[e];
+        if (!t) continue;
+        Request& R = S.reqs[t];
+        if (R.cancel_req && !R.cancel_sent) {
+            S.hjobs[e].cancelled = 1;
+            R.cancel_sent = true;
+            sent.push_back(t);
+        }
+    }
+    // ---- directory of live entries sorted by first ray
+    int nd = 0;
+    std::vector<std::pair<long long, int>> dir;
+    for (int e = 0; e < kMaxEntries; ++e)
+        if (S.entry_ticket[e]) dir.push_back({S.hjobs[e].ray_begin, e});
+    std::sort(dir.begin(), dir.end());
+    for (auto& d : dir) {
+        S.hdir_begin[nd] = d.first;
+        S.hdir_job[nd] = d.second;
+        ++nd;
+    }
+    if (nd == 0) return TARTARUS_OK;
+    const long long first = S.first_ray, total = S.next_ray;
+    const tartarus_solver sv = S.solver;
+    lk.unlock();
+
+    HIP_TRY(hipMemcpyAsync(S.djobs, S.hjobs, sizeof(DevJob) * kMaxEntries, hipMemcpyHostToDevice, S.stream));
+    for (int e : fresh)
+        HIP_TRY(hipMemcpyAsync(S.dremaining + e, S.hremaining + e, sizeof(unsigned int), hipMemcpyHostToDevice, S.stream));
+    HIP_TRY(hipMemcpyAsync(S.ddir_begin, S.hdir_begin, sizeof(long long) * nd, hipMemcpyHostToDevice, S.stream));
+    HIP_TRY(hipMemcpyAsync(S.ddir_job, S.hdir_job, sizeof(int) * nd, hipMemcpyHostToDevice, S.stream));
+    HIP_TRY(tartarus_launch_fill_u64(S.dhead, 0ull, 1, S.stream));
+    LaunchArgs A;
+    tartarus_metric m0;
+    std::memset(&m0, 0, sizeof(m0));
+    fill_args(A, &m0, &sv);
+    A.jobs = S.djobs;
+    A.jc = S.djc;
+    A.njobs = kMaxEntries;
+    A.chunk = 64;
+    A.refill_min = 16;
+    A.first_ray = first;
+    A.total_rays = total;
+    A.head = S.dhead;
+    A.slots = S.slots;
+    A.slot_live = S.slot_live;
+    A.step_budget = kEpochAttempts;
+    A.dir_begin = S.ddir_begin;
+    A.dir_job = S.ddir_job;
+    A.ndir = nd;
+    if (!fresh.empty()) HIP_TRY(tartarus_launch_setup(TARTARUS_METRIC_KERR, &A, S.stream));
+    HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, sv.precision, &A, S.grid, S.block, S.stream));
+    HIP_TRY(hipMemcpyAsync(S.hremaining, S.dremaining, sizeof(unsigned int) * kMaxEntries, hipMemcpyDeviceToHost,
+                           S.stream));
+    HIP_TRY(hipMemcpyAsync(S.hhead, S.dhead, sizeof(unsigned long long), hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    // requests whose rays have all finished: shade their disk crossings
+    std::vector<int> done;
+    for (int e = 0; e < kMaxEntries; ++e)
+        if (S.entry_ticket[e] && S.hremaining[e] == 0) done.push_back(e);
+    for (int e : done) HIP_TRY(tartarus_launch_shade(&A, e, 1, S.hjobs[e].ray_count, S.stream));
+    if (!done.empty()) HIP_TRY(hipStreamSynchronize(S.stream));
+
+    lk.lock();
+    const long long taken = (long long)*S.hhead;
+    S.first_ray = first + std::min(taken, total - first);
+    for (int e : done) {
+        const uint64_t t = S.entry_ticket[e];
+        finish_request(S, t, S.reqs[t]);
+    }
+    for (uint64_t t : sent) S.reqs[t].cancel_acked = true;
+    S.done_cv.notify_all();
+    return TARTARUS_OK;
+}
+
+void server_main()
+{
+    Server& S = g_srv;
+    std::unique_lock<std::mutex> lk(S.mu);
+    if (!S.dev_ready) {
+        int rc = server_alloc(S.solver.precision);
+        if (rc) {
+            S.dev_error = tartarus_last_error();
+            S.running = false;
+            S.done_cv.notify_all();
+            return;
+        }
+    }
+    while (S.running) {
+        if (S.queue.empty() && !any_live(S)) {
+            S.cv.wait(lk, [&] { return !S.running || !S.queue.empty() || any_live(S); });
+            continue;
+        }
+        int rc = server_round(lk);
+        if (rc) {
+            S.dev_error = tartarus_last_error();
+            S.running = false;
+            S.done_cv.notify_all();
+            break;
+        }
+    }
+}
+
+bool same_solver(const tartarus_solver& a, const tartarus_solver& b)
+{
+    return a.rtol == b.rtol && a.atol == b.atol && a.h0_frac == b.h0_frac && a.horizon_factor == b.horizon_factor &&
+           a.r_escape == b.r_escape && a.event_tol == b.event_tol && a.max_steps == b.max_steps &&
+           a.precision == b.precision && a.method == b.method;
+}
+
+}  // namespace
+
+extern "C" int tartarus_submit(const tartarus_metric* metric, const tartarus_camera* cam, const tartarus_disk* disk,
+                               const tartarus_solver* solver, const tartarus_outputs* out, uint64_t* ticket)
+{
+    int rc = validate_all(metric, cam, 1, disk, solver);
+    if (rc) return rc;
+    if ((rc = check_outputs(out))) return rc;
+    if (!ticket) return fail(TARTARUS_E_INVALID, "ticket is NULL");
+    if (metric->kind != TARTARUS_METRIC_KERR) return fail(TARTARUS_E_INVALID, "serving takes analytic Kerr requests");
+    if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    Server& S = g_srv;
+    std::unique_lock<std::mutex> lk(S.mu);
+    if (!S.dev_error.empty()) return fail(TARTARUS_E_DEVICE, "serving stopped after a device error: " + S.dev_error);
+    if (S.have_solver && !same_solver(S.solver, *solver))
+        return fail(TARTARUS_E_INVALID, "requests of one serving session must share the solver settings");
+    Request R;
+    R.metric = *metric;
+    R.cam = *cam;
+    R.disk = *disk;
+    R.solver = *solver;
+    R.out = *out;
+    R.nrays = (long long)cam->nx * cam->ny;
+    R.bytes = (size_t)R.nrays * output_bytes_per_ray();
+    // the slot arena is allocated when the scheduler starts; estimate it beforehand
+    const size_t arena = S.dev_ready ? S.arena_bytes : (size_t)g_dev.cus * 512 * (SLOT_DOUBLES * 8 + 4);
+    if (R.bytes + arena > g_dev.budget)
+        return fail(TARTARUS_E_TOO_LARGE, "request needs more than the HBM budget");
+    if (R.nrays > 0xffffffffll) return fail(TARTARUS_E_TOO_LARGE, "request has too many rays");
+    R.t_submit = now_ns();
+    const uint64_t t = S.next_ticket++;
+    S.reqs[t] = R;
+    S.queue.push_back(t);
+    if (!S.have_solver) {
+        S.solver = *solver;
+        S.have_solver = true;
+    }
+    if (!S.running) {
+        if (S.th.joinable()) S.th.join();
+        S.running = true;
+        S.th = std::thread(server_main);
+    }
+    S.cv.notify_all();
+    *ticket = t;
+    return TARTARUS_OK;
+}
+
+extern "C" int tartarus_poll(uint64_t ticket, int* state)
+{
+    if (!state) return fail(TARTARUS_E_INVALID, "state is NULL");
+    Server& S = g_srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(TARTARUS_E_NOT_FOUND, "unknown ticket");
+    if (!S.dev_error.empty() && it->second.state != 2) return fail(TARTARUS_E_DEVICE, S.dev_error);
+    *state = it->second.state;
+    return TARTARUS_OK;
+}
+
+extern "C" int tartarus_wait(uint64_t ticket, int64_t timeout_ms)
+{
+    Server& S = g_srv;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(TARTARUS_E_NOT_FOUND, "unknown ticket");
+    auto pred = [&] { return S.reqs[ticket].state == 2 || !S.dev_error.empty(); };
+    if (timeout_ms < 0)
+        S.done_cv.wait(lk, pred);
+    else if (!S.done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred))
+        return fail(TARTARUS_E_AGAIN, "request not done yet");
+    if (S.reqs[ticket].state != 2) return fail(TARTARUS_E_DEVICE, S.dev_error);
+    return TARTARUS_OK;
+}
+
+extern "C" int tartarus_cancel(uint64_t ticket)
+{
+    Server& S = g_srv;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(TARTARUS_E_NOT_FOUND, "unknown ticket");
+    Request& R = it->second;
+    if (R.state == 2) return TARTARUS_OK;
+    if (R.state == 0) {
+        S.queue.erase(std::find(S.queue.begin(), S.queue.end(), ticket));
+        R.state = 2;
+        R.t_done = now_ns();
+        S.done_cv.notify_all();
+        return TARTARUS_OK;
+    }
+    // running: from the next epoch on its rays are dropped without writing
+    // outputs; return once such an epoch has completed (or the request ended)
+    R.cancel_req = true;
+    S.cv.notify_all();
+    S.done_cv.wait(lk, [&] { return S.reqs[ticket].cancel_acked || S.reqs[ticket].state == 2 || !S.dev_error.empty(); });
+    return TARTARUS_OK;
+}
+
+extern "C" int tartarus_ticket_times(uint64_t ticket, int64_t stamps[3])
+{
+    if (!stamps) return fail(TARTARUS_E_INVALID, "stamps is NULL");
+    Server& S = g_srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(TARTARUS_E_NOT_FOUND, "unknown ticket");
+    stamps[0] = it->second.t_submit;
+    stamps[1] = it->second.t_admit;
+    stamps[2] = it->second.t_done;
+    return TARTARUS_OK;
+}
+
+namespace {
+void server_stop()
+{
+    Server& S = g_srv;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.running = false;
+        S.cv.notify_all();
+    }
+    if (S.th.joinable()) S.th.join();
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.dev_ready) server_free();
+    S.queue.clear();
+    S.reqs.clear();
+    for (auto& e : S.entry_ticket) e = 0;
+    S.used_bytes = 0;
+    S.next_ray = S.first_ray = 0;
+    S.have_solver = false;
+    S.dev_error.clear();
+}
+}  // namespace

@@ -1,0 +1,758 @@
+// trace_kernel.hip -- the persistent ray-queue integrator (gfx950) and its
+// set-up and shading passes.
+//
+// A trace is three launches on one stream:
+//   1. job_setup: per camera / request, the observer's metric and ZAMO tetrad
+//      (Sec. 2.2), r_+, the disk's inner edge and the Page-Thorne constants.
+//   2. trace_persistent: one lane integrates one ray at a time.  A wavefront
+//      takes ray ids from a global atomic queue head in chunks; when a lane's
+//      ray terminates, its outputs are written by ray id and the lane is
+//      refilled, so divergent step counts do not leave lanes idle until the
+//      slowest ray of the wave is done.  Per ray: camera initial conditions,
+//      Dormand-Prince 5(4) steps with the elementary controller, horizon /
+//      escape / equatorial events on accepted steps located on the step's
+//      cubic Hermite interpolant, and the constraint residual |H| at each
+//      accepted state (Secs. 2.2, 3.2, 4.1).
+//   3. shade: redshift g (Eq. (15)) and Novikov-Thorne flux g^4 F(r)
+//      (Eqs. (11), (16)) of every recorded disk crossing, and the pixel
+//      intensity; a coalesced pass over the rays instead of divergent work
+//      inside the integrator.
+// Per-ray arithmetic never depends on other lanes, so results are
+// bit-identical for every launch shape and batch composition.
+//
+// Precision: PREC = 0 evaluates every stage in FP64.  PREC = 1 evaluates the
+// stages of far-field steps in FP32 (stages32) while the state update, error
+// norm, controller, events and shading stay FP64.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "kerr.hpp"
+#include "kerr32.hpp"
+#include "table.hpp"
+
+namespace tartarus {
+
+// Dormand & Prince (1980) 5(4) coefficients.
+constexpr double A21 = 1.0 / 5.0;
+constexpr double A31 = 3.0 / 40.0, A32 = 9.0 / 40.0;
+constexpr double A41 = 44.0 / 45.0, A42 = -56.0 / 15.0, A43 = 32.0 / 9.0;
+constexpr double A51 = 19372.0 / 6561.0, A52 = -25360.0 / 2187.0, A53 = 64448.0 / 6561.0, A54 = -212.0 / 729.0;
+constexpr double A61 = 9017.0 / 3168.0, A62 = -355.0 / 33.0, A63 = 46732.0 / 5247.0, A64 = 49.0 / 176.0,
+                 A65 = -5103.0 / 18656.0;
+constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0, B5 = -2187.0 / 6784.0,
+                 B6 = 11.0 / 84.0;
+// error weights b - b* (fifth minus embedded fourth order)
+constexpr double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0, E5 = -17253.0 / 339200.0,
+                 E6 = 22.0 / 525.0, E7 = -1.0 / 40.0;
+
+enum { CLS_ESCAPED = 0, CLS_CAPTURED = 1, CLS_FAILED = 2 };
+
+struct Ray {
+    double t, r, th, ph, pr, pth, pt, pph;
+    Deriv<double> k;   // right-hand side at the current state (first same as last)
+    double cth;        // cos(theta) at the current state
+    double lam, h;
+    double hmax, hgate;
+    double a, rp;      // spin and horizon radius r_+
+    float guard_r, guard_th;  // mixed precision: FP32 only while |p_r| >= guard_r and |p_theta| >= guard_th
+    int n_acc, n_rej, n_f32, n_cross, n_hits, rej_prev, max_hits, job;
+    int k32;           // R.k was evaluated in FP32 (mixed precision)
+    long long local;
+};
+
+template <int KIND>
+struct MetricOps {
+    TableView T;
+    __device__ __forceinline__ void rhs(double a, double r, double th, double pr, double pth, double pt, double pph,
+                                        Deriv<double>& d, double& H, double& c) const
+    {
+        if (KIND == 0)
+            kerr_rhs64(a, r, th, pr, pth, pt, pph, d, H, c);
+        else
+            table_rhs64(T, r, th, pr, pth, pt, pph, d, H, c);
+    }
+    __device__ __forceinline__ void metric(double a, double r, double th, double g[5]) const
+    {
+        if (KIND == 0) {
+            kerr_metric64(a, r, th, g);
+        } else {
+            double gr[5], gt[5];
+            table_metric<false>(T, r, th, g, gr, gt);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// per-job constants
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ void job_setup(const DevJob* jobs, JobConst* jc, int njobs, const double* table, int nr, int nth,
+                          double r_min, double r_max)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    const DevJob& J = jobs[j];
+    MetricOps<KIND> M;
+    if (KIND == 1) M.T = make_table_view(table, nr, nth, r_min, r_max);
+    JobConst C;
+    M.metric(J.a, J.r_obs, J.theta_obs, C.g);
+    // ZAMO tetrad (Eqs. (7)-(10)); e_(t)^phi = omega e_(t)^t with omega = -g_tphi / g_phph
+    const double omega = -C.g[1] / C.g[4];
+    C.ett = 1.0 / sqrt(fma(omega * omega, C.g[4], -C.g[0]));
+    C.etp = omega * C.ett;
+    C.err = 1.0 / sqrt(C.g[2]);
+    C.ehh = 1.0 / sqrt(C.g[3]);
+    C.epp = 1.0 / sqrt(C.g[4]);
+    double s, c;
+    sincos64(J.theta_obs, &s, &c);
+    C.c2_obs = c * c;
+    C.is2_obs = 1.0 / (s * s);
+    C.rp = horizon_radius(J.a);
+    C.r_in = J.disk_r_in > 0.0 ? J.disk_r_in : isco_radius(J.a);
+    C.x0 = sqrt(C.r_in);
+    nt_flux_constants(J.a, C.xi, C.coef);
+    jc[j] = C;
+}
+
+// Covariant momentum of pixel (alpha, beta) (Eqs. (4)-(5) and the lowering with
+// Eq. (6)), negated for backward tracing.  Shared by the integrator and the
+// shading pass so both obtain the same p_t, p_phi.
+__device__ __forceinline__ void pixel_momentum(const JobConst& C, double D, double al, double be, double p[4])
+{
+    const double iD = 1.0 / D;
+    const double plr = sqrt(1.0 - (al * al + be * be) * (iD * iD));
+    const double put = C.ett;
+    const double pur = C.err * plr;
+    const double puh = C.ehh * (be * iD);
+    const double pup = fma(C.epp, -al * iD, C.etp);
+    p[0] = -fma(C.g[0], put, C.g[1] * pup);
+    p[1] = -(C.g[2] * pur);
+    p[2] = -(C.g[3] * puh);
+    p[3] = -fma(C.g[1], put, C.g[4] * pup);
+}
+
+__device__ __forceinline__ void pixel_coords(const DevJob& J, long long pix, double& al, double& be)
+{
+    const int i = (int)(pix % J.nx), j = (int)(pix / J.nx);
+    al = J.nx > 1 ? J.alpha_min + (double)i * (J.alpha_max - J.alpha_min) / (double)(J.nx - 1) : J.alpha_min;
+    be = J.ny > 1 ? J.beta_min + (double)j * (J.beta_max - J.beta_min) / (double)(J.ny - 1) : J.beta_min;
+}
+
+// ---------------------------------------------------------------------------
+// event location on the step's cubic Hermite interpolant
+// ---------------------------------------------------------------------------
+// y(s) = y0 + s (h d0 + s (c2 + s c3)), s in [0, 1], the Hermite interpolant
+// through (y_n, h k1) and (y_n+1, h k7) in monomial form.
+struct Cubic {
+    double y0, c1, c2, c3;
+    __device__ __forceinline__ Cubic(double y0_, double d0, double y1, double d1, double h)
+    {
+        y0 = y0_;
+        c1 = h * d0;
+        c2 = fma(3.0, y1 - y0_, -h * fma(2.0, d0, d1));
+        c3 = fma(2.0, y0_ - y1, h * (d0 + d1));
+    }
+    __device__ __forceinline__ double at(double s) const { return fma(s, fma(s, fma(s, c3, c2), c1), y0); }
+    __device__ __forceinline__ double slope(double s) const { return fma(s, fma(3.0 * s, c3, 2.0 * c2), c1); }
+};
+
+// Root of y(s) = target in (0, 1]: y(0) lies strictly on the start side
+// ("above": y > target) and y(1) does not.  The bracket [lo, hi] always keeps
+// the start side at lo; each iteration takes a Newton step on the cubic when it
+// stays inside the bracket and bisects otherwise.  Stops when the Newton
+// correction or the bracket is below tol in the affine parameter (tol is set
+// below the event tolerance).  At most 64 iterations.
+__device__ __forceinline__ double locate_root(const Cubic& p, double target, bool above, double h, double tol)
+{
+    double lo = 0.0, hi = 1.0;
+    const double f0 = p.y0 - target, f1 = p.at(1.0) - target;
+    double s = (f0 != f1) ? f0 / (f0 - f1) : 0.5;
+    if (!(s > 0.0 && s < 1.0)) s = 0.5;
+    for (int it = 0; it < 64; ++it) {
+        const double f = p.at(s) - target;
+        const bool same = above ? (f > 0.0) : (f < 0.0);
+        if (same)
+            lo = s;
+        else
+            hi = s;
+        if ((hi - lo) * h <= tol) return 0.5 * (lo + hi);
+        double sn = s - f / p.slope(s);
+        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+        if (fabs(sn - s) * h <= 0.25 * tol) return sn;
+        s = sn;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Equatorial crossing for polar angles outside (-pi/2, 3pi/2), where the sign
+// of cos(theta) is not the sign of pi/2 - theta: plain bisection on cos.
+__device__ __noinline__ double locate_equator_wide(const Cubic& p, bool north_start, double h, double tol)
+{
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 80 && (hi - lo) * h > tol; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const double v = cos(p.at(mid));
+        const bool same = north_start ? (v > 0.0) : (v < 0.0);
+        lo = same ? mid : lo;
+        hi = same ? hi : mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+__device__ __forceinline__ int find_job(const LaunchArgs& A, long long gid)
+{
+    if (A.dir_begin) {
+        int lo = 0, hi = A.ndir - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.dir_begin[mid] <= gid)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return A.dir_job[lo];
+    }
+    int lo = 0, hi = A.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.jobs[mid].ray_begin <= gid)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// one ray
+// ---------------------------------------------------------------------------
+template <int KIND>
+__device__ void ray_init(Ray& R, long long gid, const LaunchArgs& A, const MetricOps<KIND>& M)
+{
+    const int jb = find_job(A, gid);
+    const DevJob& J = A.jobs[jb];
+    const JobConst& C = A.jc[jb];
+    const long long pix = gid - J.ray_begin;
+    double al, be, p[4];
+    pixel_coords(J, pix, al, be);
+    pixel_momentum(C, J.r_obs, al, be, p);
+    R.t = 0.0;
+    R.r = J.r_obs;
+    R.th = J.theta_obs;
+    R.ph = 0.0;
+    R.pt = p[0];
+    R.pr = p[1];
+    R.pth = p[2];
+    R.pph = p[3];
+    R.a = J.a;
+    R.rp = C.rp;
+    R.k32 = 0;
+    // Carter's constant from the initial state sets the polar turning-point guard
+    const double Q = fma(R.pth, R.pth, C.c2_obs * (R.pph * R.pph * C.is2_obs - R.a * R.a * R.pt * R.pt));
+    R.guard_th = (float)(A.turn_th * sqrt(fmax(Q, 1e-12)));
+    R.guard_r = (float)(A.turn_r * fabs(R.pt));
+    double H;
+    M.rhs(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, H, R.cth);
+    R.hmax = fabs(H);
+    R.hgate = R.r >= 1.5 * R.rp ? fabs(H) : 0.0;
+    R.lam = 0.0;
+    R.h = A.h0_frac * J.r_obs;
+    R.n_acc = R.n_rej = R.n_f32 = R.n_cross = R.n_hits = R.rej_prev = 0;
+    R.max_hits = J.max_hits;
+    R.job = jb;
+    R.local = pix;
+}
+
+__device__ void ray_finish(const Ray& R, const LaunchArgs& A, int cls, double fr, double fth, double fph)
+{
+    const DevJob& J = A.jobs[R.job];
+    const long long q = R.local;
+    J.cls[q] = cls;
+    J.n_hits[q] = R.n_hits;
+    J.final_rtp[3 * q + 0] = fr;
+    J.final_rtp[3 * q + 1] = fth;
+    J.final_rtp[3 * q + 2] = fph;
+    J.h_drift[q] = R.hmax;
+    J.h_gate[q] = R.hgate;
+    J.n_accept[q] = R.n_acc;
+    J.n_reject[q] = R.n_rej;
+    J.n_fp32[q] = R.n_f32;
+    J.n_cross[q] = R.n_cross;
+    for (int k = R.n_hits; k < 3; ++k) {
+        J.hit_r[3 * q + k] = 0.0;
+        J.hit_g[3 * q + k] = 0.0;
+        J.hit_flux[3 * q + k] = 0.0;
+        J.hit_lambda[3 * q + k] = 0.0;
+        J.hit_order[3 * q + k] = 0;
+    }
+    if (J.remaining) atomicSub(J.remaining, 1u);
+}
+
+// An equatorial crossing at radius rr: recorded when it lies on the disk and a
+// slot is free (shading happens in the shade pass).
+__device__ __forceinline__ void record_crossing(Ray& R, const LaunchArgs& A, double rr, double lam_hit)
+{
+    R.n_cross++;
+    if (R.n_hits >= R.max_hits) return;
+    const DevJob& J = A.jobs[R.job];
+    if (!(rr >= A.jc[R.job].r_in && rr <= J.disk_r_out)) return;
+    const long long q = 3 * R.local + R.n_hits;
+    J.hit_r[q] = rr;
+    J.hit_lambda[q] = lam_hit;
+    J.hit_order[q] = R.n_cross;
+    R.n_hits++;
+}
+
+// ---- mixed precision ------------------------------------------------------
+// The regime is decided per ray from its own state only (never from its
+// wavefront), so a ray's arithmetic is the same in any batch.  FP32 stages are
+// used where r >= r_switch_factor * r_+ at the start of the step, away from
+// radial and polar turning points.
+__device__ __forceinline__ bool far_field(const Ray& R, const LaunchArgs& A)
+{
+    return R.r >= A.r_switch_factor * R.rp && fabs(R.pr) >= (double)R.guard_r && fabs(R.pth) >= (double)R.guard_th;
+}
+
+// One attempted DP45 step whose six new stage evaluations run in FP32 (on-shell
+// far-field form, kerr32.hpp).  The stage increments are summed in FP32 and
+// added to the FP64 state; the t component carries only delta_t in FP32 and
+// its constant part -p_t h is added in FP64.  The error vector feeds the FP64
+// norm; H(y5) and cos(theta5) are evaluated in FP64 for the constraint monitor
+// and the event tests.
+__device__ __forceinline__ void stages32(const Ray& R, double h, Deriv<double>& y5, Deriv<double>& k7d,
+                                         Deriv<double>& e, double& H5, double& c5)
+{
+    const float a = (float)R.a, hf = (float)h;
+    const float r0 = (float)R.r, th0 = (float)R.th, pr0 = (float)R.pr, pth0 = (float)R.pth;
+    const float pt = (float)R.pt, pph = (float)R.pph;
+    Deriv<float> k1;
+    k1.t = (float)(R.k.t + R.pt);
+    k1.r = (float)R.k.r;
+    k1.th = (float)R.k.th;
+    k1.ph = (float)R.k.ph;
+    k1.pr = (float)R.k.pr;
+    k1.pth = (float)R.k.pth;
+    Deriv<float> k2, k3, k4, k5, k6, k7;
+    const float a21 = (float)A21, a31 = (float)A31, a32 = (float)A32, a41 = (float)A41, a42 = (float)A42,
+                a43 = (float)A43, a51 = (float)A51, a52 = (float)A52, a53 = (float)A53, a54 = (float)A54,
+                a61 = (float)A61, a62 = (float)A62, a63 = (float)A63, a64 = (float)A64, a65 = (float)A65;
+    kerr_rhs32(a, fmaf(hf, a21 * k1.r, r0), fmaf(hf, a21 * k1.th, th0), fmaf(hf, a21 * k1.pr, pr0),
+               fmaf(hf, a21 * k1.pth, pth0), pt, pph, k2);
+#define TT_S3(c, y) fmaf(hf, fmaf(a32, k2.c, a31 * k1.c), y)
+    kerr_rhs32(a, TT_S3(r, r0), TT_S3(th, th0), TT_S3(pr, pr0), TT_S3(pth, pth0), pt, pph, k3);
+#define TT_S4(c, y) fmaf(hf, fmaf(a43, k3.c, fmaf(a42, k2.c, a41 * k1.c)), y)
+    kerr_rhs32(a, TT_S4(r, r0), TT_S4(th, th0), TT_S4(pr, pr0), TT_S4(pth, pth0), pt, pph, k4);
+#define TT_S5(c, y) fmaf(hf, fmaf(a54, k4.c, fmaf(a53, k3.c, fmaf(a52, k2.c, a51 * k1.c))), y)
+    kerr_rhs32(a, TT_S5(r, r0), TT_S5(th, th0), TT_S5(pr, pr0), TT_S5(pth, pth0), pt, pph, k5);
+#define TT_S6(c, y) fmaf(hf, fmaf(a65, k5.c, fmaf(a64, k4.c, fmaf(a63, k3.c, fmaf(a62, k2.c, a61 * k1.c)))), y)
+    kerr_rhs32(a, TT_S6(r, r0), TT_S6(th, th0), TT_S6(pr, pr0), TT_S6(pth, pth0), pt, pph, k6);
+    const float b1 = (float)B1, b3 = (float)B3, b4 = (float)B4, b5 = (float)B5, b6 = (float)B6;
+#define TT_INC(c) (double)(hf * fmaf(b6, k6.c, fmaf(b5, k5.c, fmaf(b4, k4.c, fmaf(b3, k3.c, b1 * k1.c)))))
+    y5.t = fma(-h, R.pt, R.t) + TT_INC(t);
+    y5.r = R.r + TT_INC(r);
+    y5.th = R.th + TT_INC(th);
+    y5.ph = R.ph + TT_INC(ph);
+    y5.pr = R.pr + TT_INC(pr);
+    y5.pth = R.pth + TT_INC(pth);
+    kerr_rhs32(a, (float)y5.r, (float)y5.th, (float)y5.pr, (float)y5.pth, pt, pph, k7);
+    const float e1 = (float)E1, e3 = (float)E3, e4 = (float)E4, e5 = (float)E5, e6 = (float)E6, e7 = (float)E7;
+#define TT_E32(c) (double)(hf * fmaf(e7, k7.c, fmaf(e6, k6.c, fmaf(e5, k5.c, fmaf(e4, k4.c, fmaf(e3, k3.c, e1 * k1.c))))))
+    e.t = TT_E32(t);
+    e.r = TT_E32(r);
+    e.th = TT_E32(th);
+    e.ph = TT_E32(ph);
+    e.pr = TT_E32(pr);
+    e.pth = TT_E32(pth);
+    k7d.t = (double)k7.t - R.pt;
+    k7d.r = (double)k7.r;
+    k7d.th = (double)k7.th;
+    k7d.ph = (double)k7.ph;
+    k7d.pr = (double)k7.pr;
+    k7d.pth = (double)k7.pth;
+    H5 = kerr_H64(R.a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, c5);
+#undef TT_S3
+#undef TT_S4
+#undef TT_S5
+#undef TT_S6
+#undef TT_INC
+#undef TT_E32
+}
+
+// One attempted DP45 step with FP64 stages.  Writes the fifth-order state y5
+// (dynamic components), k7 = f(y5), H(y5), cos(theta5) and the error vector.
+template <int KIND>
+__device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
+                                         Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
+{
+    const Deriv<double>& k1 = R.k;
+    const double a = R.a;
+    Deriv<double> k2, k3, k4, k5, k6;
+    double Hd, cd;
+    M.rhs(a, fma(h, A21 * k1.r, R.r), fma(h, A21 * k1.th, R.th), fma(h, A21 * k1.pr, R.pr),
+          fma(h, A21 * k1.pth, R.pth), R.pt, R.pph, k2, Hd, cd);
+#define TT_S3(c) fma(h, fma(A32, k2.c, A31 * k1.c), R.c)
+    M.rhs(a, TT_S3(r), TT_S3(th), TT_S3(pr), TT_S3(pth), R.pt, R.pph, k3, Hd, cd);
+#define TT_S4(c) fma(h, fma(A43, k3.c, fma(A42, k2.c, A41 * k1.c)), R.c)
+    M.rhs(a, TT_S4(r), TT_S4(th), TT_S4(pr), TT_S4(pth), R.pt, R.pph, k4, Hd, cd);
+#define TT_S5(c) fma(h, fma(A54, k4.c, fma(A53, k3.c, fma(A52, k2.c, A51 * k1.c))), R.c)
+    M.rhs(a, TT_S5(r), TT_S5(th), TT_S5(pr), TT_S5(pth), R.pt, R.pph, k5, Hd, cd);
+#define TT_S6(c) fma(h, fma(A65, k5.c, fma(A64, k4.c, fma(A63, k3.c, fma(A62, k2.c, A61 * k1.c)))), R.c)
+    M.rhs(a, TT_S6(r), TT_S6(th), TT_S6(pr), TT_S6(pth), R.pt, R.pph, k6, Hd, cd);
+#define TT_Y5(c) fma(h, fma(B6, k6.c, fma(B5, k5.c, fma(B4, k4.c, fma(B3, k3.c, B1 * k1.c)))), R.c)
+    y5.t = TT_Y5(t);
+    y5.r = TT_Y5(r);
+    y5.th = TT_Y5(th);
+    y5.ph = TT_Y5(ph);
+    y5.pr = TT_Y5(pr);
+    y5.pth = TT_Y5(pth);
+    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+#define TT_E(c) h * fma(E7, k7.c, fma(E6, k6.c, fma(E5, k5.c, fma(E4, k4.c, fma(E3, k3.c, E1 * k1.c)))))
+    e.t = TT_E(t);
+    e.r = TT_E(r);
+    e.th = TT_E(th);
+    e.ph = TT_E(ph);
+    e.pr = TT_E(pr);
+    e.pth = TT_E(pth);
+#undef TT_S3
+#undef TT_S4
+#undef TT_S5
+#undef TT_S6
+#undef TT_Y5
+#undef TT_E
+}
+
+__device__ __forceinline__ double sq_ratio(double e, double y0, double y1, double atol, double rtol)
+{
+    const double z = e * rcp64(fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
+    return z * z;
+}
+
+// x^(-1/5) for 1e-6 <= x <= 1e5: an FP32 estimate refined by two Newton steps
+// on y^-5 = x (y <- y (6 - x y^5) / 5), which take the ~1e-7 relative error of
+// the estimate below an ulp of the double result.
+__device__ __forceinline__ double pow_m_one_fifth(double x)
+{
+    double y = (double)exp2f(-0.2f * log2f((float)x));
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double y2 = y * y;
+        const double y5 = y2 * y2 * y;
+        y = y * fma(-x, y5, 6.0) * 0.2;
+    }
+    return y;
+}
+
+// Step-size factor of the elementary controller: min(fmx, max(0.2, 0.9 err^-1/5)).
+// Outside [1e-6, 1e5] the clamps decide the result without the power.
+__device__ __forceinline__ double step_factor(double err, double fmx)
+{
+    if (err < 1e-6) return fmx;
+    if (err > 1e5) return 0.2;
+    return fmin(fmx, fmax(0.2, 0.9 * pow_m_one_fifth(err)));
+}
+
+// One attempt; returns true when the ray has terminated (outputs written).
+template <int KIND, int PREC>
+__device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
+{
+    if ((long long)R.n_acc + R.n_rej >= A.max_steps) {
+        ray_finish(R, A, CLS_FAILED, R.r, R.th, R.ph);
+        return true;
+    }
+    const double h = R.h;
+    Deriv<double> y5, k7, e;
+    double H5, c5;
+    bool used32 = false;
+    if (PREC == 1 && KIND == 0 && far_field(R, A)) {
+        stages32(R, h, y5, k7, e, H5, c5);
+        used32 = true;
+    } else {
+        if (PREC == 1 && R.k32) {
+            // leaving the FP32 regime: re-evaluate the first stage in FP64
+            double Hd;
+            M.rhs(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth);
+            R.k32 = 0;
+        }
+        stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
+    }
+    R.n_f32 += used32 ? 1 : 0;
+    const double atol = A.atol, rtol = A.rtol;
+    double acc = sq_ratio(e.t, R.t, y5.t, atol, rtol);
+    acc += sq_ratio(e.r, R.r, y5.r, atol, rtol);
+    acc += sq_ratio(e.th, R.th, y5.th, atol, rtol);
+    acc += sq_ratio(e.ph, R.ph, y5.ph, atol, rtol);
+    acc += sq_ratio(e.pr, R.pr, y5.pr, atol, rtol);
+    acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
+    // p_t and p_phi have zero error (their derivatives vanish identically)
+    const double err = sqrt(acc * 0.125);
+    if (!(err <= 1.0)) {
+        // rejected; a NaN or infinite error also lands here
+        R.n_rej++;
+        R.h = h * (isnan(err) ? 0.2 : step_factor(err, 1.0));
+        R.rej_prev = 1;
+        if (R.h < 1e-14 * fmax(1.0, fabs(R.lam))) {
+            ray_finish(R, A, CLS_FAILED, R.r, R.th, R.ph);
+            return true;
+        }
+        return false;
+    }
+    R.n_acc++;
+    if (!(isfinite(y5.t) && isfinite(y5.r) && isfinite(y5.th) && isfinite(y5.ph) && isfinite(y5.pr) &&
+          isfinite(y5.pth))) {
+        ray_finish(R, A, CLS_FAILED, R.r, R.th, R.ph);
+        return true;
+    }
+
+    // ---- constraint residual (Eq. (17)) at the accepted state
+    const double aH = fabs(H5);
+    R.hmax = fmax(R.hmax, aH);
+    if (y5.r >= 1.5 * R.rp) R.hgate = fmax(R.hgate, aH);
+
+    // ---- events on the accepted step [lam, lam + h]
+    double r_stop = A.horizon_factor * R.rp;
+    if (KIND == 1 && A.tab_r_min > r_stop) r_stop = A.tab_r_min;
+    const double r_esc = A.r_escape;
+    const bool hz = (R.r - r_stop > 0.0) && (y5.r - r_stop <= 0.0);
+    const bool es = (R.r - r_esc < 0.0) && (y5.r - r_esc >= 0.0);
+    const bool dk = R.max_hits > 0 && ((R.cth > 0.0 && c5 <= 0.0) || (R.cth < 0.0 && c5 >= 0.0));
+    if (hz | es | dk) {
+        const double tol = 0.125 * A.event_tol;
+        const Cubic pr_(R.r, R.k.r, y5.r, k7.r, h);
+        double s_term = 2.0, s_disk = 2.0;
+        int term = 0;
+        // at most one of the two radial events can bracket a root in one step
+        if (hz) {
+            s_term = locate_root(pr_, r_stop, true, h, tol);
+            term = 1;
+        } else if (es) {
+            s_term = locate_root(pr_, r_esc, false, h, tol);
+            term = 2;
+        }
+        if (dk) {
+            const Cubic pth_(R.th, R.k.th, y5.th, k7.th, h);
+            const bool wide = !(R.th > -M_PI_2 && R.th < 1.5 * M_PI && y5.th > -M_PI_2 && y5.th < 1.5 * M_PI);
+            s_disk = wide ? locate_equator_wide(pth_, R.cth > 0.0, h, tol)
+                          : locate_root(pth_, M_PI_2, R.cth < 0.0, h, tol);
+        }
+        // events in root order; a disk crossing at or before the terminal root
+        // is recorded, one after it is dropped
+        if (dk && s_disk <= s_term) record_crossing(R, A, pr_.at(s_disk), fma(s_disk, h, R.lam));
+        if (term) {
+            const Cubic pth_(R.th, R.k.th, y5.th, k7.th, h);
+            const Cubic pph_(R.ph, R.k.ph, y5.ph, k7.ph, h);
+            ray_finish(R, A, term == 1 ? CLS_CAPTURED : CLS_ESCAPED, pr_.at(s_term), pth_.at(s_term),
+                       pph_.at(s_term));
+            return true;
+        }
+    }
+
+    // ---- elementary controller
+    const double fac = step_factor(err, R.rej_prev ? 1.0 : 10.0);
+    R.lam += h;
+    R.t = y5.t;
+    R.r = y5.r;
+    R.th = y5.th;
+    R.ph = y5.ph;
+    R.pr = y5.pr;
+    R.pth = y5.pth;
+    R.k = k7;
+    R.k32 = used32 ? 1 : 0;
+    R.cth = c5;
+    R.h = h * fac;
+    R.rej_prev = 0;
+    return false;
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt()
+{
+    const unsigned int lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+static_assert(sizeof(Ray) <= SLOT_DOUBLES * sizeof(double), "parked ray state must fit a slot");
+
+__device__ __forceinline__ void park(const Ray& R, double* slot)
+{
+    const double* src = reinterpret_cast<const double*>(&R);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Ray) / sizeof(double)); ++i) slot[i] = src[i];
+}
+
+__device__ __forceinline__ void unpark(Ray& R, const double* slot)
+{
+    double* dst = reinterpret_cast<double*>(&R);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Ray) / sizeof(double)); ++i) dst[i] = slot[i];
+}
+
+// A ray of a cancelled job terminates without writing its outputs.
+__device__ __forceinline__ bool drop_if_cancelled(const Ray& R, const LaunchArgs& A)
+{
+    const DevJob& J = A.jobs[R.job];
+    if (!J.cancelled) return false;
+    if (J.remaining) atomicSub(J.remaining, 1u);
+    return true;
+}
+
+// Occupancy target per instantiation: the analytic FP64 integrator fits 168
+// VGPRs (3 waves per SIMD) without spilling in its loop; the mixed and
+// tabulated ones need more registers and run at 2.
+template <int KIND, int PREC>
+struct WavesPerEU {
+    static constexpr int value = (KIND == 0 && PREC == 0) ? 3 : 2;
+};
+
+template <int KIND, int PREC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<KIND, PREC>::value)))
+trace_persistent(LaunchArgs A)
+{
+    MetricOps<KIND> M;
+    if (KIND == 1) M.T = make_table_view(A.table, A.nr, A.nth, A.tab_r_min, A.tab_r_max);
+    Ray R;
+    bool active = false;
+    bool parked = false;       // this lane used its step budget for this launch
+    bool exhausted = false;
+    long long budget = A.step_budget;
+    const long long slot = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (A.slots && A.slot_live[slot]) {
+        unpark(R, A.slots + slot * SLOT_DOUBLES);
+        A.slot_live[slot] = 0u;
+        active = !drop_if_cancelled(R, A);
+    }
+    // this wavefront's current chunk of ray ids [next, end) (wave-uniform values)
+    long long next = 0, end = 0;
+    const long long n_rays = A.total_rays - A.first_ray;
+    for (;;) {
+        if (!exhausted) {
+            const unsigned long long need = __ballot(!active && !parked);
+            const int nneed = __popcll(need);
+            if (nneed > 0 && (nneed >= A.refill_min || !__any(active))) {
+                const int rank = __popcll(need & lanemask_lt());
+                long long id = -1;
+                const long long avail = end - next;
+                if (!active && !parked && rank < avail) id = next + rank;
+                const int taken = (int)(avail < nneed ? avail : nneed);
+                next += taken;
+                const int rem = nneed - taken;
+                if (rem > 0) {
+                    const int leader = __ffsll((long long)need) - 1;
+                    unsigned long long c0 = 0;
+                    if ((int)__lane_id() == leader) c0 = atomicAdd(A.head, (unsigned long long)A.chunk);
+                    c0 = __shfl(c0, leader);
+                    if ((long long)c0 >= n_rays) {
+                        exhausted = true;
+                        next = end = 0;
+                    } else {
+                        next = (long long)c0;
+                        end = next + A.chunk < n_rays ? next + A.chunk : n_rays;
+                        const long long r2 = rank - taken;
+                        if (!active && !parked && r2 >= 0 && r2 < end - next) id = next + r2;
+                        const long long got = (end - next) < rem ? (end - next) : rem;
+                        next += got;
+                    }
+                }
+                if (id >= 0) {
+                    ray_init<KIND>(R, A.first_ray + id, A, M);
+                    active = !drop_if_cancelled(R, A);
+                }
+            }
+        }
+        if (!__any(active)) {
+            if (exhausted || !__any(!parked)) break;
+            continue;
+        }
+        if (active) {
+            active = !ray_step<KIND, PREC>(R, A, M);
+            if (active && A.slots && --budget == 0) {
+                park(R, A.slots + slot * SLOT_DOUBLES);
+                A.slot_live[slot] = 1u;
+                active = false;
+                parked = true;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// shading: g and g^4 F(r) of the recorded crossings, pixel intensity
+// ---------------------------------------------------------------------------
+// blockIdx.y selects the job (job0 + blockIdx.y); x covers its rays.
+__global__ void shade_kernel(const DevJob* jobs, const JobConst* jc, int job0)
+{
+    const int jb = job0 + blockIdx.y;
+    const DevJob& J = jobs[jb];
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= J.ray_count) return;
+    if (J.cancelled) return;
+    const JobConst& C = jc[jb];
+    const int n = J.n_hits[q];
+    double inten = 0.0;
+    if (n > 0) {
+        double al, be, p[4];
+        pixel_coords(J, q, al, be);
+        pixel_momentum(C, J.r_obs, al, be, p);
+        for (int k = 0; k < n; ++k) {
+            const double rr = J.hit_r[3 * q + k];
+            const double g = redshift(J.a, rr, p[0], p[3]);
+            const double F = nt_flux_pre(J.a, C.x0, C.xi, C.coef, rr);
+            const double g2 = g * g;
+            const double flux = g2 * g2 * F;
+            J.hit_g[3 * q + k] = g;
+            J.hit_flux[3 * q + k] = flux;
+            inten += flux;
+        }
+    }
+    J.intensity[q] = inten;
+}
+
+}  // namespace tartarus
+
+using namespace tartarus;
+
+extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hipStream_t stream)
+{
+    const int n = args->njobs;
+    const int blocks = (n + 63) / 64;
+    if (kind == 0)
+        hipLaunchKernelGGL((job_setup<0>), dim3(blocks), dim3(64), 0, stream, args->jobs, (JobConst*)args->jc, n,
+                           nullptr, 0, 0, 0.0, 0.0);
+    else
+        hipLaunchKernelGGL((job_setup<1>), dim3(blocks), dim3(64), 0, stream, args->jobs, (JobConst*)args->jc, n,
+                           args->table, args->nr, args->nth, args->tab_r_min, args->tab_r_max);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t tartarus_launch_trace(int kind, int prec, const LaunchArgs* args, int grid, int block,
+                                            hipStream_t stream)
+{
+    if (kind == 0 && prec == 0)
+        hipLaunchKernelGGL((trace_persistent<0, 0>), dim3(grid), dim3(block), 0, stream, *args);
+    else if (kind == 0 && prec == 1)
+        hipLaunchKernelGGL((trace_persistent<0, 1>), dim3(grid), dim3(block), 0, stream, *args);
+    else if (kind == 1)
+        hipLaunchKernelGGL((trace_persistent<1, 0>), dim3(grid), dim3(block), 0, stream, *args);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Shade jobs [job0, job0 + njobs), each with at most max_rays rays.
+extern "C" hipError_t tartarus_launch_shade(const LaunchArgs* args, int job0, int njobs, long long max_rays,
+                                            hipStream_t stream)
+{
+    if (njobs <= 0 || max_rays <= 0) return hipSuccess;
+    const long long bx = (max_rays + 255) / 256;
+    if (bx > 0x7fffffffll || njobs > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(shade_kernel, dim3((unsigned)bx, (unsigned)njobs), dim3(256), 0, stream, args->jobs, args->jc,
+                       job0);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t tartarus_occupancy(int kind, int prec, int block, int* blocks_per_cu)
+{
+    const void* f = nullptr;
+    if (kind == 0 && prec == 0) f = (const void*)trace_persistent<0, 0>;
+    else if (kind == 0 && prec == 1) f = (const void*)trace_persistent<0, 1>;
+    else f = (const void*)trace_persistent<1, 0>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, 0);
+}

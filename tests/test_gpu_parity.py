@@ -1,0 +1,198 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+FP64 path: identical classes off the edge band and relative error <= 1e-9 in
+emission radius, redshift, final theta (phi: 1e-9 * max(1, |phi|)), flux as
+max |dI| / max(I), and |d h_drift| <= 1e-12.  Mixed path: the same rules at
+1e-4.  Full-size images are checked on seeded samples of pixels (with their 8
+neighbours traced by the oracle for the edge band) in the launch configuration
+the benchmark uses.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import assert_parity, class_key, compare, edge_band
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL, FP64_HTOL, MIXED_TOL = 1e-9, 1e-12, 1e-4
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_08989_amd import tartarus as T
+    T.tartarus_init(0, 0)
+    return T
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_trace(T, a, cams, disk, solver, precision=0, launch=None, table=None):
+    import torch
+    cams = cams if isinstance(cams, list) else [cams]
+    n = sum(c["nx"] * c["ny"] for c in cams)
+    out = T.alloc_outputs(n)
+    metric = T.make_metric(a) if table is None else T.make_metric(a, *table)
+    T.tartarus_trace(metric, [T.make_camera(c) for c in cams], T.make_disk(disk), T.make_solver(solver, precision),
+                     out, launch=launch)
+    torch.cuda.synchronize()
+    return T.to_numpy(out)
+
+
+def oracle_trace(orc, a, cams, disk, solver, ray_ids=None, table=None):
+    cams = cams if isinstance(cams, list) else [cams]
+    m = orc.make_metric(a) if table is None else orc.make_metric(a, *table)
+    return orc.trace(m, [orc.make_camera(c) for c in cams], orc.make_disk(disk), orc.make_solver(solver),
+                     ray_ids=ray_ids)
+
+
+def full_image_parity(T, orc, a, cam, disk, solver, precision=0, tol=FP64_TOL, htol=FP64_HTOL):
+    g = gpu_trace(T, a, cam, disk, solver, precision)
+    o = oracle_trace(orc, a, cam, disk, solver)
+    band = edge_band(class_key(o).reshape(cam["ny"], cam["nx"])).ravel()
+    res = compare(g, o, band, tol)
+    say(res)
+    assert_parity(res, tol, htol)
+    return g, o
+
+
+def sampled_parity(T, orc, a, cam, disk, solver, precision, nsample, seed, tol, htol=None, g=None):
+    """Full image on the GPU; the oracle traces sampled pixels and their neighbours."""
+    nx, ny = cam["nx"], cam["ny"]
+    if g is None:
+        g = gpu_trace(T, a, cam, disk, solver, precision)
+    rng = np.random.default_rng(seed)
+    ii = rng.integers(1, nx - 1, nsample)
+    jj = rng.integers(1, ny - 1, nsample)
+    offs = [(dj, di) for dj in (-1, 0, 1) for di in (-1, 0, 1)]
+    ids = np.array([(j + dj) * nx + (i + di) for i, j in zip(ii, jj) for dj, di in offs], dtype=np.int64)
+    uniq, inv = np.unique(ids, return_inverse=True)
+    o_u = oracle_trace(orc, a, cam, disk, solver, ray_ids=uniq)
+    key_u = class_key(o_u)
+    key9 = key_u[inv].reshape(nsample, 9)
+    band = np.any(key9 != key9[:, 4:5], axis=1)
+    centre = inv.reshape(nsample, 9)[:, 4]
+    o = {k: v[centre] for k, v in o_u.items()}
+    gs = {k: v[uniq[centre]] for k, v in g.items()}
+    res = compare(gs, o, band, tol)
+    say(res)
+    assert_parity(res, tol, htol)
+    return g, res
+
+
+# ------------------------------------------------------------------ FP64 images
+def test_schwarzschild_64_full(T, orc):
+    w = W.WORKLOADS["schwarzschild_64"]
+    say("case schwarzschild_64 fp64")
+    g, o = full_image_parity(T, orc, w["a"], w["cameras"][0], w["disk"], w["solver"])
+    assert np.array_equal(g["n_accept"], o["n_accept"]) or np.mean(g["n_accept"] == o["n_accept"]) > 0.99
+
+
+def test_kerr_ragged_with_disk(T, orc):
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=37, ny=29)
+    say("case kerr09 37x29 fp64")
+    g, o = full_image_parity(T, orc, w["a"], cam, w["disk"], w["solver"])
+    assert (o["n_hits"] > 0).sum() > 50
+
+
+def test_single_pixel_and_single_row(T, orc):
+    w = W.WORKLOADS["kerr09_512"]
+    for nx, ny in ((1, 1), (17, 1), (1, 5)):
+        cam = dict(w["cameras"][0], nx=nx, ny=ny)
+        say("case kerr09", nx, ny)
+        g = gpu_trace(T, w["a"], cam, w["disk"], w["solver"])
+        o = oracle_trace(orc, w["a"], cam, w["disk"], w["solver"])
+        assert np.array_equal(g["cls"], o["cls"]) and np.array_equal(g["n_hits"], o["n_hits"])
+        m = o["n_hits"] > 0
+        if m.any():
+            assert np.abs(g["hit_r"][m, 0] / o["hit_r"][m, 0] - 1).max() < FP64_TOL
+
+
+def test_max_steps_forces_failed(T, orc):
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=8, ny=8)
+    sv = dict(w["solver"], max_steps=5)
+    g = gpu_trace(T, w["a"], cam, w["disk"], sv)
+    o = oracle_trace(orc, w["a"], cam, w["disk"], sv)
+    assert np.all(g["cls"] == 2) and np.all(o["cls"] == 2)
+    assert np.all(g["n_accept"] + g["n_reject"] == 5)
+    assert np.array_equal(g["n_accept"], o["n_accept"])
+    # After a fixed number of attempts the states sit at slightly different
+    # affine parameters: the first error estimate (err ~ 1e-5) comes from a
+    # ~1e9-fold cancellation in the phi component, so the step sizes of two
+    # correct implementations differ at ~1e-7 relative.
+    assert np.allclose(g["final_rtp"], o["final_rtp"], rtol=1e-5, atol=1e-9)
+
+
+def test_kerr09_512_sampled_fp64(T, orc):
+    w = W.WORKLOADS["kerr09_512"]
+    say("case kerr09_512 fp64 sampled")
+    sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], w["solver"], 0, 300, 1, FP64_TOL, FP64_HTOL)
+
+
+def test_launch_shape_invariance(T):
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=96, ny=80)
+    ref = gpu_trace(T, w["a"], cam, w["disk"], w["solver"])
+    for bt, bpc, ch, rf in ((64, 1, 64, 1), (128, 0, 1024, 32), (256, 1, 96, 64), (256, 2, 4096, 8)):
+        say("launch", bt, bpc, ch, rf)
+        g = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], launch=T.make_launch(bt, bpc, ch, rf))
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), k
+
+
+# ------------------------------------------------------------------ tabulated metric
+def test_table_build_matches_oracle(T, orc):
+    import torch
+    a = 0.7
+    rp = orc.horizon(a)
+    nr, nth, r_min, r_max = 64, 32, 1.1 * rp, 2000.0
+    tab = torch.zeros(5 * nr * nth * 4, dtype=torch.float64, device="cuda")
+    T.tartarus_build_kerr_table(a, nr, nth, r_min, r_max, tab)
+    torch.cuda.synchronize()
+    g = tab.cpu().numpy().reshape(5, nr, nth, 4)
+    o = orc.build_kerr_table(a, nr, nth, r_min, r_max)
+    big = np.abs(o).max(axis=(1, 2), keepdims=True)
+    assert np.all(np.abs(g - o) <= 1e-13 * np.abs(o) + 1e-15 * big)
+
+
+# ------------------------------------------------------------------ mixed precision
+def test_mixed_small_full_image(T, orc):
+    w = W.WORKLOADS["kerr0998_2048"]
+    cam = dict(w["cameras"][0], nx=48, ny=41)
+    say("case kerr0998 48x41 mixed")
+    g, o = full_image_parity(T, orc, w["a"], cam, w["disk"], w["solver"], precision=1, tol=MIXED_TOL, htol=None)
+    assert g["n_fp32"].sum() > 0.3 * (g["n_accept"] + g["n_reject"]).sum()
+
+
+def test_kerr09_512_sampled_mixed(T, orc):
+    w = W.WORKLOADS["kerr09_512"]
+    say("case kerr09_512 mixed sampled")
+    sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], w["solver"], 1, 200, 2, MIXED_TOL)
+
+
+def test_kerr0998_2048_sampled_fp64_and_mixed(T, orc):
+    w = W.WORKLOADS["kerr0998_2048"]
+    say("case kerr0998_2048 fp64 sampled")
+    sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], w["solver"], 0, 150, 3, FP64_TOL, FP64_HTOL)
+    say("case kerr0998_2048 mixed sampled")
+    sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], w["solver"], 1, 150, 3, MIXED_TOL)
+
+
+def test_gate_tolerance_fp64_sampled(T, orc):
+    """The benchmark's tolerance (rtol 3e-10): parity and the |H| <= 1e-8 gate."""
+    w = W.WORKLOADS["kerr09_512"]
+    sv = dict(w["solver"], rtol=3e-10, atol=3e-12)
+    say("case kerr09_512 fp64 rtol 3e-10 sampled")
+    g, res = sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], sv, 0, 120, 4, FP64_TOL, FP64_HTOL)
+    assert g["h_gate"][g["cls"] != 2].max() <= 1e-8
