@@ -572,6 +572,7 @@ struct Request {
     long long ray_begin = 0;
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     bool cancel_req = false, cancel_sent = false, cancel_acked = false;
+    bool too_large = false;  // can never fit the budget next to the slot arena
 };
 
 struct Server {
@@ -700,6 +701,14 @@ int server_round(std::unique_lock<std::mutex>& lk)
     while (!S.queue.empty()) {
         const uint64_t t = S.queue.front();
         Request& R = S.reqs[t];
+        if (R.bytes + S.arena_bytes > g_dev.budget) {
+            // submit checked against an estimate of the arena; this one never fits
+            S.queue.pop_front();
+            R.too_large = true;
+            R.state = 2;
+            R.t_done = now_ns();
+            continue;
+        }
         int entry = -1;
         for (int e = 0; e < kMaxEntries; ++e)
             if (!S.entry_ticket[e]) { entry = e; break; }
@@ -855,7 +864,7 @@ extern "C" int tartarus_submit(const tartarus_metric* metric, const tartarus_cam
     R.nrays = (long long)cam->nx * cam->ny;
     R.bytes = (size_t)R.nrays * output_bytes_per_ray();
     // the slot arena is allocated when the scheduler starts; estimate it beforehand
-    const size_t arena = S.dev_ready ? S.arena_bytes : (size_t)g_dev.cus * 512 * (SLOT_DOUBLES * 8 + 4);
+    const size_t arena = S.dev_ready ? S.arena_bytes : (size_t)g_dev.cus * 768 * (SLOT_DOUBLES * 8 + 4);
     if (R.bytes + arena > g_dev.budget)
         return fail(TARTARUS_E_TOO_LARGE, "request needs more than the HBM budget");
     if (R.nrays > 0xffffffffll) return fail(TARTARUS_E_TOO_LARGE, "request has too many rays");
@@ -885,6 +894,7 @@ extern "C" int tartarus_poll(uint64_t ticket, int* state)
     auto it = S.reqs.find(ticket);
     if (it == S.reqs.end()) return fail(TARTARUS_E_NOT_FOUND, "unknown ticket");
     if (!S.dev_error.empty() && it->second.state != 2) return fail(TARTARUS_E_DEVICE, S.dev_error);
+    if (it->second.too_large) return fail(TARTARUS_E_TOO_LARGE, "request does not fit the HBM budget");
     *state = it->second.state;
     return TARTARUS_OK;
 }
@@ -901,6 +911,7 @@ extern "C" int tartarus_wait(uint64_t ticket, int64_t timeout_ms)
     else if (!S.done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred))
         return fail(TARTARUS_E_AGAIN, "request not done yet");
     if (S.reqs[ticket].state != 2) return fail(TARTARUS_E_DEVICE, S.dev_error);
+    if (S.reqs[ticket].too_large) return fail(TARTARUS_E_TOO_LARGE, "request does not fit the HBM budget");
     return TARTARUS_OK;
 }
 

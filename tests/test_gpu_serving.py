@@ -1,0 +1,115 @@
+"""Serving through the C ABI (tartarus_submit / poll / wait / cancel): requests
+of mixed resolution, spin and inclination share one device queue; each
+request's outputs are bit-identical to tracing it alone."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture()
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_08989_amd import tartarus as T
+    T.tartarus_init(0, 0)
+    yield T
+    T.tartarus_shutdown()
+
+
+def stream_requests(n, seed, res=(24, 32, 48, 64)):
+    reqs = W.request_stream(seed, n, rate_per_s=1e6, resolutions=res)
+    return reqs
+
+
+def alone(T, r, precision):
+    import torch
+    cam = r["camera"]
+    out = T.alloc_outputs(cam["nx"] * cam["ny"])
+    T.tartarus_trace(T.make_metric(r["a"]), T.make_camera(cam), T.make_disk(r["disk"]),
+                     T.make_solver(r["solver"], precision), out)
+    torch.cuda.synchronize()
+    return T.to_numpy(out)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_requests_alone_equal_in_mix(T, precision):
+    reqs = stream_requests(7, seed=precision)
+    outs, tickets = [], []
+    for r in reqs:
+        cam = r["camera"]
+        o = T.alloc_outputs(cam["nx"] * cam["ny"])
+        outs.append(o)
+        tickets.append(T.tartarus_submit(T.make_metric(r["a"]), T.make_camera(cam), T.make_disk(r["disk"]),
+                                         T.make_solver(r["solver"], precision), o))
+    for t in tickets:
+        T.tartarus_wait(t, 120000)
+        assert T.tartarus_poll(t) == 2
+        st = T.tartarus_ticket_times(t)
+        assert 0 < st[0] <= st[1] <= st[2]
+    for r, o in zip(reqs, outs):
+        g = T.to_numpy(o)
+        ref = alone(T, r, precision)
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (r["id"], k)
+        assert np.all(g["cls"] != 2)
+
+
+def test_arrivals_during_running_work_overlap(T):
+    """A request submitted while a large one runs is admitted and finishes before it."""
+    big = stream_requests(1, seed=11, res=(384,))[0]
+    small = stream_requests(1, seed=12, res=(16,))[0]
+    ob = T.alloc_outputs(384 * 384)
+    os_ = T.alloc_outputs(16 * 16)
+    mk = lambda r: (T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
+                    T.make_solver(r["solver"]))
+    tb = T.tartarus_submit(*mk(big), ob)
+    time.sleep(0.002)
+    ts = T.tartarus_submit(*mk(small), os_)
+    T.tartarus_wait(ts, 120000)
+    T.tartarus_wait(tb, 120000)
+    sb, ss = T.tartarus_ticket_times(tb), T.tartarus_ticket_times(ts)
+    assert ss[1] < sb[2]           # admitted before the large one completed
+    ref = alone(T, small, 0)
+    g = T.to_numpy(os_)
+    for k in ref:
+        assert np.array_equal(ref[k], g[k]), k
+
+
+def test_cancel_and_errors(T):
+    r = stream_requests(1, seed=3, res=(256,))[0]
+    o = T.alloc_outputs(256 * 256)
+    mk = lambda r, prec=0: (T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
+                            T.make_solver(r["solver"], prec))
+    t = T.tartarus_submit(*mk(r), o)
+    T.tartarus_cancel(t)
+    assert T.tartarus_poll(t) == 2
+    # the session keeps working after a cancel
+    r2 = stream_requests(1, seed=4, res=(20,))[0]
+    o2 = T.alloc_outputs(400)
+    t2 = T.tartarus_submit(*mk(r2), o2)
+    T.tartarus_wait(t2, 60000)
+    ref = alone(T, r2, 0)
+    assert np.array_equal(ref["hit_r"], T.to_numpy(o2)["hit_r"])
+    # a different solver in the same session is refused
+    with pytest.raises(T.TartarusError) as e:
+        T.tartarus_submit(*mk(r2, prec=1), o2)
+    assert e.value.code == T.E_INVALID
+    with pytest.raises(T.TartarusError) as e:
+        T.tartarus_poll(987654321)
+    assert e.value.code == T.E_NOT_FOUND
+
+
+def test_budget_too_small(T):
+    T.tartarus_init(0, 1 << 20)   # 1 MiB: smaller than the ray-slot arena
+    r = stream_requests(1, seed=5, res=(16,))[0]
+    o = T.alloc_outputs(256)
+    with pytest.raises(T.TartarusError) as e:
+        T.tartarus_submit(T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
+                          T.make_solver(r["solver"]), o)
+    assert e.value.code == T.E_TOO_LARGE
