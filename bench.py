@@ -51,17 +51,21 @@ def algorithmic_flops(out: dict) -> float:
                  + out["n_cross"].sum() * FLOP_EVENT + out["n_hits"].sum() * FLOP_HIT)
 
 
-def time_leg(T, torch, args_tuple, out, steps, warmup):
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_leg(T, torch, args_tuple, out, steps, warmup, launch=None):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        T.tartarus_trace(*args_tuple, out)
+        T.tartarus_trace(*args_tuple, out, launch=launch)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(steps):
-        T.tartarus_trace(*args_tuple, out)
+        T.tartarus_trace(*args_tuple, out, launch=launch)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -90,6 +94,40 @@ def cpu_baseline(w, solver, seconds: float) -> dict:
                       f"plain FP64 C oracle, OpenMP over pixels, {dt:.1f} s"}
 
 
+def serving_leg(T, torch, W, value_rtol8: float, n_requests: int, load: float = 0.8, seed: int = 0) -> dict:
+    """Poisson stream of image requests (resolution uniform over 64^2..1024^2,
+    spin, inclination, disk size drawn per request) submitted at their arrival
+    times through tartarus_submit; latency = done - submit per request."""
+    mean_rays = float(np.mean([r * r for r in W.RESOLUTIONS]))
+    rate = load * value_rtol8 / mean_rays
+    reqs = W.request_stream(seed, n_requests, rate)
+    outs = [T.alloc_outputs(r["camera"]["nx"] * r["camera"]["ny"]) for r in reqs]
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.perf_counter()
+    for r, o in zip(reqs, outs):
+        delay = r["arrival_s"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(T.tartarus_submit(T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
+                                         T.make_solver(r["solver"]), o))
+    for t in tickets:
+        T.tartarus_wait(t, 120000)
+    stamps = np.array([T.tartarus_ticket_times(t) for t in tickets], dtype=np.float64)
+    lat_ms = (stamps[:, 2] - stamps[:, 0]) * 1e-6
+    warm = 10 if len(lat_ms) > 20 else 0
+    rays = sum(r["camera"]["nx"] * r["camera"]["ny"] for r in reqs)
+    span = (stamps[:, 2].max() - stamps[:, 0].min()) * 1e-9
+    failed = int(sum(int((T.to_numpy({"cls": o["cls"]})["cls"] == 2).sum()) for o in outs))
+    T.tartarus_shutdown()
+    T.tartarus_init(0, 0)
+    return {"requests": len(reqs), "load": load, "arrival_rate_per_s": rate, "precision": "fp64",
+            "rtol": reqs[0]["solver"]["rtol"], "p50_latency_ms": float(np.percentile(lat_ms[warm:], 50)),
+            "p99_latency_ms": float(np.percentile(lat_ms[warm:], 99)),
+            "max_latency_ms": float(lat_ms[warm:].max()), "rays_per_s": rays / span, "failed_rays": failed,
+            "note": "latency = completion - submission; first 10 requests are warm-up"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +137,11 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="time only the headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape")
+    ap.add_argument("--launch", default="", help="force the launch shape block,blocks_per_cu,chunk,refill_min")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-latency leg")
+    ap.add_argument("--serving-requests", type=int, default=96)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one device copy of this many MiB (calibrates FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -109,6 +152,17 @@ def main():
 
     import workloads as W
     from paper_2609_08989_amd import tartarus as T
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nb}))
+        return
 
     T.tartarus_init(0, 0)
     w = W.WORKLOADS["kerr09_512"]
@@ -121,11 +175,17 @@ def main():
     # ---- headline: FP64 at the gate tolerance
     leg_args = (metric, cams, disk, T.make_solver(gate_solver, T.PREC_FP64))
     tuned = {}
-    if not args.no_autotune:
+    launch = None
+    if args.launch:
+        launch = T.make_launch(*[int(v) for v in args.launch.split(",")])
+        tuned["fp64"] = [launch.block_threads, launch.blocks_per_cu, launch.chunk, launch.refill_min]
+    elif not args.no_autotune:
+        log("bench: autotune")
         # untimed: pick the launch shape for this workload (part of the warm-up)
         L = T.tartarus_autotune(*leg_args, out)
         tuned["fp64"] = [L.block_threads, L.blocks_per_cu, L.chunk, L.refill_min]
-    wall, kern_ms = time_leg(T, torch, leg_args, out, args.steps, args.warmup)
+    log("bench: headline leg (fp64, gate tolerance)", tuned)
+    wall, kern_ms = time_leg(T, torch, leg_args, out, args.steps, args.warmup, launch)
     o = T.to_numpy(out)
     ms_per_step = wall * 1e3 / args.steps
     value = n * args.steps / wall
@@ -153,6 +213,7 @@ def main():
         legs = {}
         for name, prec in (("fp64_rtol1e-8", T.PREC_FP64), ("mixed_rtol1e-8", T.PREC_MIXED)):
             la = (metric, cams, disk, T.make_solver(w["solver"], prec))
+            log("bench: leg", name)
             if prec == T.PREC_MIXED and not args.no_autotune:
                 L = T.tartarus_autotune(*la, out)
                 tuned["mixed"] = [L.block_threads, L.blocks_per_cu, L.chunk, L.refill_min]
@@ -168,10 +229,15 @@ def main():
         legs["mixed_rtol1e-8_over_fp64_gate"] = legs["mixed_rtol1e-8"]["rays_per_s"] / value
         result["legs"] = legs
 
+    if not args.no_serving:
+        log("bench: serving leg")
+        result["serving"] = serving_leg(T, torch, W, value_rtol8=result.get("legs", {}).get(
+            "fp64_rtol1e-8", {}).get("rays_per_s", value), n_requests=args.serving_requests)
     if tuned:
         result["launch_shape"] = {k: dict(zip(("block_threads", "blocks_per_cu", "chunk", "refill_min"), v))
                                   for k, v in tuned.items()}
     if not args.no_cpu:
+        log("bench: cpu baseline")
         result["cpu_baseline"] = cpu_baseline(w, gate_solver, args.cpu_seconds)
     print(json.dumps(result))
 

@@ -635,16 +635,21 @@ trace_persistent(LaunchArgs A)
                 next += taken;
                 const int rem = nneed - taken;
                 if (rem > 0) {
+                    // One-shot traces fetch a chunk and keep the rest for later
+                    // refills.  In serving epochs a wavefront may exit with all
+                    // lanes parked, so it fetches exactly the ids it hands out:
+                    // an id taken from the queue is never left unassigned.
+                    const long long fetch = A.slots ? (long long)rem : (A.chunk > rem ? A.chunk : rem);
                     const int leader = __ffsll((long long)need) - 1;
                     unsigned long long c0 = 0;
-                    if ((int)__lane_id() == leader) c0 = atomicAdd(A.head, (unsigned long long)A.chunk);
+                    if ((int)__lane_id() == leader) c0 = atomicAdd(A.head, (unsigned long long)fetch);
                     c0 = __shfl(c0, leader);
                     if ((long long)c0 >= n_rays) {
                         exhausted = true;
                         next = end = 0;
                     } else {
                         next = (long long)c0;
-                        end = next + A.chunk < n_rays ? next + A.chunk : n_rays;
+                        end = next + fetch < n_rays ? next + fetch : n_rays;
                         const long long r2 = rank - taken;
                         if (!active && !parked && r2 >= 0 && r2 < end - next) id = next + r2;
                         const long long got = (end - next) < rem ? (end - next) : rem;

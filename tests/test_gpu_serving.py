@@ -113,3 +113,21 @@ def test_budget_too_small(T):
         T.tartarus_submit(T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
                           T.make_solver(r["solver"]), o)
     assert e.value.code == T.E_TOO_LARGE
+
+
+def test_request_larger_than_the_lane_count(T):
+    """More rays than device lanes: lanes refill in partial waves and park at
+    epoch ends; every ray id handed out must be traced (no request may stall)."""
+    big = stream_requests(1, seed=21, res=(704,))[0]
+    small = stream_requests(2, seed=22, res=(40,))
+    mk = lambda r: (T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
+                    T.make_solver(r["solver"]))
+    outs = [T.alloc_outputs(704 * 704)] + [T.alloc_outputs(1600) for _ in small]
+    ts = [T.tartarus_submit(*mk(r), o) for r, o in zip([big] + small, outs)]
+    for t in ts:
+        T.tartarus_wait(t, 60000)
+    for r, o in zip([big] + small, outs):
+        ref = alone(T, r, 0)
+        g = T.to_numpy(o)
+        for k in ("cls", "n_hits", "hit_r", "final_rtp", "n_accept"):
+            assert np.array_equal(ref[k], g[k]), k
