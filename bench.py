@@ -55,6 +55,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+SHAPE_KEYS = ("block_threads", "blocks_per_cu", "chunk", "refill_min", "order")
+
+
+def shape(L):
+    return [L.block_threads, L.blocks_per_cu, L.chunk, L.refill_min, L.order]
+
+
 def time_leg(T, torch, args_tuple, out, steps, warmup, launch=None):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -137,7 +144,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="time only the headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shape")
-    ap.add_argument("--launch", default="", help="force the launch shape block,blocks_per_cu,chunk,refill_min")
+    ap.add_argument("--launch", default="", help="force the launch shape block,blocks_per_cu,chunk,refill_min[,order]")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-latency leg")
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -178,12 +185,12 @@ def main():
     launch = None
     if args.launch:
         launch = T.make_launch(*[int(v) for v in args.launch.split(",")])
-        tuned["fp64"] = [launch.block_threads, launch.blocks_per_cu, launch.chunk, launch.refill_min]
+        tuned["fp64"] = shape(launch)
     elif not args.no_autotune:
         log("bench: autotune")
         # untimed: pick the launch shape for this workload (part of the warm-up)
         L = T.tartarus_autotune(*leg_args, out)
-        tuned["fp64"] = [L.block_threads, L.blocks_per_cu, L.chunk, L.refill_min]
+        tuned["fp64"] = shape(L)
     log("bench: headline leg (fp64, gate tolerance)", tuned)
     wall, kern_ms = time_leg(T, torch, leg_args, out, args.steps, args.warmup, launch)
     o = T.to_numpy(out)
@@ -211,12 +218,18 @@ def main():
     # ---- extra legs at the config tolerance rtol = 1e-8
     if not args.no_extra:
         legs = {}
+        # the headline trace with the work queue in pixel order instead of cost order
+        sh = dict(zip(SHAPE_KEYS, tuned.get("fp64", [0, 0, 0, 0, 0])))
+        lp = T.make_launch(sh["block_threads"], sh["blocks_per_cu"], sh["chunk"], sh["refill_min"], T.ORDER_PIXEL)
+        log("bench: leg gate_pixel_order")
+        wl, km = time_leg(T, torch, leg_args, out, args.steps, args.warmup, lp)
+        legs["gate_pixel_order"] = {"rays_per_s": n * args.steps / wl, "kernel_ms": km}
         for name, prec in (("fp64_rtol1e-8", T.PREC_FP64), ("mixed_rtol1e-8", T.PREC_MIXED)):
             la = (metric, cams, disk, T.make_solver(w["solver"], prec))
             log("bench: leg", name)
             if prec == T.PREC_MIXED and not args.no_autotune:
                 L = T.tartarus_autotune(*la, out)
-                tuned["mixed"] = [L.block_threads, L.blocks_per_cu, L.chunk, L.refill_min]
+                tuned["mixed"] = shape(L)
             wl, km = time_leg(T, torch, la, out, args.steps, args.warmup)
             ol = T.to_numpy(out)
             attl = ol["n_accept"] + ol["n_reject"]
@@ -234,8 +247,7 @@ def main():
         result["serving"] = serving_leg(T, torch, W, value_rtol8=result.get("legs", {}).get(
             "fp64_rtol1e-8", {}).get("rays_per_s", value), n_requests=args.serving_requests)
     if tuned:
-        result["launch_shape"] = {k: dict(zip(("block_threads", "blocks_per_cu", "chunk", "refill_min"), v))
-                                  for k, v in tuned.items()}
+        result["launch_shape"] = {k: dict(zip(SHAPE_KEYS, v)) for k, v in tuned.items()}
     if not args.no_cpu:
         log("bench: cpu baseline")
         result["cpu_baseline"] = cpu_baseline(w, gate_solver, args.cpu_seconds)

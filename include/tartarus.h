@@ -110,7 +110,7 @@ typedef struct {
 } tartarus_disk;
 
 /* Integrator settings (Sec. 3.2).  rtol > 0, atol > 0, h0_frac > 0,
- * horizon_factor >= 1, r_escape > r_obs, event_tol > 0, max_steps >= 1
+ * horizon_factor >= 1, r_obs < r_escape <= 1e15, event_tol > 0, max_steps >= 1
  * (attempted steps, accepted + rejected).  precision: TARTARUS_PREC_FP64, or
  * TARTARUS_PREC_MIXED (Runge-Kutta stages evaluated in FP32 in the far field;
  * state sums, error norm, controller, events and shading stay FP64).
@@ -145,12 +145,22 @@ typedef struct {
 
 /* Launch shape of the persistent integrator.  Any value <= 0 means "use the
  * tuned or default choice".  Results are bit-identical for every launch shape
- * (rays never share arithmetic). */
+ * and queue order (rays never share arithmetic).
+ *
+ * order: TARTARUS_ORDER_PIXEL hands rays out in pixel order (camera by camera,
+ * row-major); TARTARUS_ORDER_COST first sorts them into buckets by how close
+ * they pass to the critical curve (the spherical photon orbits, which the
+ * rays that take the most steps wind around) and starts the closest first, so
+ * that the longest rays do not start last and finish alone.  The default
+ * (0) is COST for traces of at least 4096 rays, else PIXEL. */
+enum { TARTARUS_ORDER_DEFAULT = 0, TARTARUS_ORDER_PIXEL = 1, TARTARUS_ORDER_COST = 2 };
+
 typedef struct {
     int block_threads;     /* 64, 128 or 256                                        */
     int blocks_per_cu;     /* resident workgroups per compute unit                  */
-    int chunk;             /* ray ids a wavefront takes from the global queue per fetch (>= 64) */
+    int chunk;             /* least ray ids a wavefront takes per fetch; ids beyond its idle lanes wait in it (1 = none wait) */
     int refill_min;        /* idle lanes that trigger a refill (1..64)              */
+    int order;             /* TARTARUS_ORDER_*                                      */
 } tartarus_launch;
 
 /* Select the device and set the HBM budget (bytes) for the serving queue

@@ -81,6 +81,8 @@ struct LaunchArgs {
     const int* dir_job;
     int ndir;
     int pad2;
+    // queue position -> ray index (relative to first_ray); null: identity
+    const unsigned int* order;
 };
 
 constexpr int SLOT_DOUBLES = 32;

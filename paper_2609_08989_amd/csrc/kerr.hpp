@@ -34,9 +34,13 @@ __device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double
     const double s2 = s * s;
     const double sig = fma(a2, c * c, r2);
     const double del = fma(r, r - 2.0, a2);
-    const double iS = rcp64(sig);
-    const double iD = rcp64(del);
-    const double is2 = rcp64(s2);
+    // 1/Sigma, 1/Delta and 1/sin^2 from one reciprocal of their product (radii
+    // are bounded by the escape radius, so the product stays in range)
+    const double sd = sig * del;
+    const double inv = rcp64(sd * s2);
+    const double iS = (del * s2) * inv;
+    const double iD = (sig * s2) * inv;
+    const double is2 = sd * inv;
     const double ra = r2 + a2;
     const double P = fma(ra, pt, a * pph);
     const double W = fma(a * s2, pt, pph);

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -22,6 +23,7 @@
 
 #include "../../include/tartarus.h"
 #include "internal.hpp"
+#include "order.hpp"
 
 using namespace tartarus;
 
@@ -33,6 +35,9 @@ extern "C" hipError_t tartarus_launch_shade(const LaunchArgs* args, int job0, in
 extern "C" hipError_t tartarus_occupancy(int kind, int prec, int block, int* blocks_per_cu);
 extern "C" hipError_t tartarus_launch_build_table(double a, int nr, int nth, double r_min, double r_max,
                                                   double* table, hipStream_t stream);
+extern "C" hipError_t tartarus_launch_order(const LaunchArgs* args, long long total, unsigned char* key,
+                                            unsigned int* count, unsigned int* cursor, unsigned int* order,
+                                            hipStream_t stream);
 extern "C" hipError_t tartarus_launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_fill_u64(unsigned long long* p, unsigned long long v, long long n,
                                                hipStream_t stream);
@@ -74,10 +79,13 @@ struct Slot {
     JobConst* djc = nullptr;             // per-job constants (device, written by the set-up kernel)
     int cap = 0;
     unsigned long long* head = nullptr;
+    unsigned char* ord = nullptr;        // cost-ordered queue: order[n] u32, key[n] u8, count and cursor
+    size_t ord_cap = 0;                  // bytes
     hipEvent_t ev = nullptr;
     bool pending = false;
 };
 constexpr int kSlots = 16;
+constexpr long long kCostOrderMin = 4096;  // default: cost-ordered queue from this many rays on
 
 struct Device {
     bool ready = false;
@@ -164,7 +172,8 @@ int check_solver(const tartarus_solver* s)
     if (!finite_pos(s->h0_frac)) return fail(TARTARUS_E_INVALID, "h0_frac must be > 0");
     if (!(std::isfinite(s->horizon_factor) && s->horizon_factor >= 1.0))
         return fail(TARTARUS_E_INVALID, "horizon_factor must be >= 1");
-    if (!finite_pos(s->r_escape)) return fail(TARTARUS_E_INVALID, "r_escape must be > 0");
+    if (!(finite_pos(s->r_escape) && s->r_escape <= 1e15))
+        return fail(TARTARUS_E_INVALID, "r_escape must be in (0, 1e15]");
     if (!finite_pos(s->event_tol)) return fail(TARTARUS_E_INVALID, "event_tol must be > 0");
     if (s->max_steps < 1) return fail(TARTARUS_E_INVALID, "max_steps must be >= 1");
     if (s->precision != TARTARUS_PREC_FP64 && s->precision != TARTARUS_PREC_MIXED)
@@ -283,8 +292,9 @@ tartarus_launch default_launch(int kind, int prec)
     tartarus_launch L;
     L.block_threads = 256;
     L.blocks_per_cu = 0;
-    L.chunk = 64;
+    L.chunk = 1;
     L.refill_min = 4;
+    L.order = TARTARUS_ORDER_DEFAULT;
     return L;
 }
 
@@ -296,7 +306,9 @@ int resolve_launch(int kind, int prec, const tartarus_launch* req, tartarus_laun
         if (req->blocks_per_cu > 0) L.blocks_per_cu = req->blocks_per_cu;
         if (req->chunk > 0) L.chunk = req->chunk;
         if (req->refill_min > 0) L.refill_min = req->refill_min;
+        if (req->order > 0) L.order = req->order;
     }
+    if (L.order < 0 || L.order > TARTARUS_ORDER_COST) return fail(TARTARUS_E_INVALID, "unknown queue order");
     if (L.block_threads != 64 && L.block_threads != 128 && L.block_threads != 256)
         return fail(TARTARUS_E_INVALID, "block_threads must be 64, 128 or 256");
     if (L.refill_min < 1 || L.refill_min > 64) return fail(TARTARUS_E_INVALID, "refill_min must be in 1..64");
@@ -336,6 +348,27 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
     A.total_rays = per * ncams;
     A.head = S->head;
     HIP_TRY(tartarus_launch_setup(kind, &A, stream));
+    const long long n = A.total_rays;
+    const bool cost = n <= 0xffffffffll &&
+                      (L.order == TARTARUS_ORDER_COST || (L.order == TARTARUS_ORDER_DEFAULT && n >= kCostOrderMin));
+    if (cost) {
+        const size_t key_bytes = ((size_t)n + 255) / 256 * 256;
+        const size_t need = (size_t)n * 4 + key_bytes + 2 * kOrderBuckets * sizeof(unsigned int);
+        if (need > S->ord_cap) {
+            if (S->ord) (void)hipFree(S->ord);
+            S->ord = nullptr;
+            S->ord_cap = 0;
+            HIP_TRY(hipMalloc(&S->ord, need));
+            S->ord_cap = need;
+        }
+        unsigned int* order = reinterpret_cast<unsigned int*>(S->ord);
+        unsigned char* key = S->ord + (size_t)n * 4;
+        unsigned int* count = reinterpret_cast<unsigned int*>(key + key_bytes);
+        unsigned int* cursor = count + kOrderBuckets;
+        HIP_TRY(tartarus_launch_fill_u32(count, 0u, kOrderBuckets, stream));
+        HIP_TRY(tartarus_launch_order(&A, n, key, count, cursor, order, stream));
+        A.order = order;
+    }
     HIP_TRY(tartarus_launch_trace(kind, prec, &A, grid, L.block_threads, stream));
     for (int c0 = 0; c0 < ncams; c0 += 65535)
         HIP_TRY(tartarus_launch_shade(&A, c0, std::min(65535, ncams - c0), per, stream));
@@ -464,7 +497,7 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
     if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;  // warm-up
     if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;
     const int blocks[] = {64, 128, 256};
-    const int chunks[] = {64, 256, 1024, 4096};
+    const int chunks[] = {1, 16, 64, 256, 1024};
     const int refills[] = {1, 8, 16, 32, 48};
     for (int pass = 0; pass < 2; ++pass) {
         for (int b : blocks) {
@@ -500,6 +533,13 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
             if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
             if (ms < best_ms) { best_ms = ms; cur = L; }
         }
+        for (int o : {(int)TARTARUS_ORDER_PIXEL, (int)TARTARUS_ORDER_COST}) {
+            tartarus_launch L = cur;
+            L.order = o;
+            float ms = 0.f;
+            if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; cur = L; }
+        }
     }
     g_dev.tuned[kind * 2 + prec] = cur;
     *best = cur;
@@ -522,6 +562,7 @@ extern "C" int tartarus_shutdown(void)
         if (S.hjobs) (void)hipHostFree(S.hjobs);
         if (S.djc) (void)hipFree(S.djc);
         if (S.head) (void)hipFree(S.head);
+        if (S.ord) (void)hipFree(S.ord);
         if (S.ev) (void)hipEventDestroy(S.ev);
         S = Slot();
     }

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
+#include "order.hpp"
 #include "kerr.hpp"
 #include "kerr32.hpp"
 #include "table.hpp"
@@ -485,10 +486,14 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
     // p_t and p_phi have zero error (their derivatives vanish identically)
     const double err = sqrt(acc * 0.125);
-    if (!(err <= 1.0)) {
+    // elementary controller, evaluated once for both outcomes: after a
+    // rejection (or for one) the step may not grow
+    const bool ok = err <= 1.0;
+    const double fac = isnan(err) ? 0.2 : step_factor(err, (ok && !R.rej_prev) ? 10.0 : 1.0);
+    if (!ok) {
         // rejected; a NaN or infinite error also lands here
         R.n_rej++;
-        R.h = h * (isnan(err) ? 0.2 : step_factor(err, 1.0));
+        R.h = h * fac;
         R.rej_prev = 1;
         if (R.h < 1e-14 * fmax(1.0, fabs(R.lam))) {
             ray_finish(R, A, CLS_FAILED, R.r, R.th, R.ph);
@@ -546,8 +551,6 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
         }
     }
 
-    // ---- elementary controller
-    const double fac = step_factor(err, R.rej_prev ? 1.0 : 10.0);
     R.lam += h;
     R.t = y5.t;
     R.r = y5.r;
@@ -657,6 +660,7 @@ trace_persistent(LaunchArgs A)
                     }
                 }
                 if (id >= 0) {
+                    if (A.order) id = (long long)A.order[id];
                     ray_init<KIND>(R, A.first_ray + id, A, M);
                     active = !drop_if_cancelled(R, A);
                 }
@@ -713,6 +717,94 @@ __global__ void shade_kernel(const DevJob* jobs, const JobConst* jc, int job0)
 }  // namespace tartarus
 
 using namespace tartarus;
+
+// ---------------------------------------------------------------------------
+// cost-ordered work queue: rays nearest the critical curve are handed out first
+// ---------------------------------------------------------------------------
+// Pass 1: bucket of every ray (from its constants of motion) and the bucket
+// histogram.  One thread per ray; LDS histogram per block, then one global add
+// per non-empty bucket.
+__global__ void __launch_bounds__(256) order_keys_kernel(const DevJob* jobs, const JobConst* jc, int njobs,
+                                                         long long total, unsigned char* key, unsigned int* count)
+{
+    __shared__ unsigned int hist[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (gid < total) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].ray_begin <= gid)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DevJob& J = jobs[lo];
+        const JobConst& C = jc[lo];
+        double al, be, p[4];
+        pixel_coords(J, gid - J.ray_begin, al, be);
+        pixel_momentum(C, J.r_obs, al, be, p);
+        // b = L / E and q = Q / E^2 are unchanged by the backward-tracing sign flip
+        const double ipt = 1.0 / p[0];
+        const double b = -p[3] * ipt;
+        const double Q = fma(p[2], p[2], C.c2_obs * (p[3] * p[3] * C.is2_obs - J.a * J.a * p[0] * p[0]));
+        const int k = cost_bucket(J.a, b, Q * ipt * ipt, C.rp);
+        key[gid] = (unsigned char)k;
+        atomicAdd(&hist[k], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && hist[threadIdx.x]) atomicAdd(&count[threadIdx.x], hist[threadIdx.x]);
+}
+
+// Pass 2: start of each bucket in the queue, highest bucket first.
+__global__ void order_scan_kernel(const unsigned int* count, unsigned int* cursor)
+{
+    if (threadIdx.x != 0) return;
+    unsigned int run = 0u;
+    for (int k = kOrderBuckets - 1; k >= 0; --k) {
+        cursor[k] = run;
+        run += count[k];
+    }
+}
+
+// Pass 3: scatter ray indices to their bucket's range.  The order inside a
+// bucket depends on atomic timing, which only changes when a ray is traced.
+__global__ void __launch_bounds__(256) order_scatter_kernel(const unsigned char* key, unsigned int* cursor,
+                                                            long long total, unsigned int* order)
+{
+    __shared__ unsigned int hist[kOrderBuckets], base[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    int k = 0;
+    unsigned int rank = 0u;
+    if (gid < total) {
+        k = key[gid];
+        rank = atomicAdd(&hist[k], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && hist[threadIdx.x])
+        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], hist[threadIdx.x]);
+    __syncthreads();
+    if (gid < total) order[base[k] + rank] = (unsigned int)gid;
+}
+
+// The three passes; count and cursor (kOrderBuckets entries each) must be zero
+// on entry to the first one.
+extern "C" hipError_t tartarus_launch_order(const LaunchArgs* args, long long total, unsigned char* key,
+                                            unsigned int* count, unsigned int* cursor, unsigned int* order,
+                                            hipStream_t stream)
+{
+    if (total <= 0) return hipSuccess;
+    const long long blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffffll || total > 0xffffffffll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(order_keys_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, args->jobs, args->jc,
+                       args->njobs, total, key, count);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, stream, count, cursor);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, key, cursor, total, order);
+    return hipGetLastError();
+}
 
 extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hipStream_t stream)
 {

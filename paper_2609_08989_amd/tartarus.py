@@ -19,6 +19,7 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_TOO_LARGE, E_NOT_FOUND, E_AGAIN = 0, -1, -2,
 ESCAPED, CAPTURED, FAILED = 0, 1, 2
 METRIC_KERR, METRIC_TABLE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+ORDER_DEFAULT, ORDER_PIXEL, ORDER_COST = 0, 1, 2
 
 
 class TartarusError(RuntimeError):
@@ -58,7 +59,7 @@ class Outputs(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("block_threads", C.c_int), ("blocks_per_cu", C.c_int), ("chunk", C.c_int),
-                ("refill_min", C.c_int)]
+                ("refill_min", C.c_int), ("order", C.c_int)]
 
 
 _lib = None
@@ -134,8 +135,8 @@ def make_solver(s: dict, precision: int = PREC_FP64) -> Solver:
                   s["r_escape"], s.get("event_tol", 1e-12), s.get("max_steps", 1_000_000), precision, 0)
 
 
-def make_launch(block_threads=0, blocks_per_cu=0, chunk=0, refill_min=0) -> Launch:
-    return Launch(block_threads, blocks_per_cu, chunk, refill_min)
+def make_launch(block_threads=0, blocks_per_cu=0, chunk=0, refill_min=0, order=0) -> Launch:
+    return Launch(block_threads, blocks_per_cu, chunk, refill_min, order)
 
 
 def alloc_outputs(n: int, device="cuda") -> dict:

@@ -57,6 +57,7 @@ def test_validate_accepts_the_workloads(T):
     (lambda m, c, d, s: setattr(s, "rtol", 0.0), "rtol"),
     (lambda m, c, d, s: setattr(s, "atol", 0.0), "atol"),
     (lambda m, c, d, s: setattr(s, "r_escape", 900.0), "r_escape"),
+    (lambda m, c, d, s: setattr(s, "r_escape", 2e15), "r_escape"),
     (lambda m, c, d, s: setattr(s, "horizon_factor", 0.9), "horizon_factor"),
     (lambda m, c, d, s: setattr(s, "max_steps", 0), "max_steps"),
     (lambda m, c, d, s: setattr(s, "precision", 5), "precision"),

@@ -150,13 +150,35 @@ def test_kerr09_512_sampled_fp64(T, orc):
 def test_launch_shape_invariance(T):
     w = W.WORKLOADS["kerr09_512"]
     cam = dict(w["cameras"][0], nx=96, ny=80)
-    ref = gpu_trace(T, w["a"], cam, w["disk"], w["solver"])
-    for bt, bpc, ch, rf in ((64, 1, 64, 1), (128, 0, 1024, 32), (256, 1, 96, 64), (256, 2, 4096, 8)):
-        say("launch", bt, bpc, ch, rf)
-        g = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], launch=T.make_launch(bt, bpc, ch, rf))
+    ref = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], launch=T.make_launch(order=T.ORDER_PIXEL))
+    for bt, bpc, ch, rf, od in ((64, 1, 64, 1, T.ORDER_COST), (128, 0, 1024, 32, T.ORDER_PIXEL),
+                                (256, 1, 96, 64, T.ORDER_COST), (256, 2, 4096, 8, T.ORDER_PIXEL),
+                                (256, 0, 64, 4, T.ORDER_COST), (256, 0, 64, 4, T.ORDER_DEFAULT)):
+        say("launch", bt, bpc, ch, rf, od)
+        g = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], launch=T.make_launch(bt, bpc, ch, rf, od))
         for k in ref:
             assert np.array_equal(ref[k], g[k]), k
 
+
+
+def test_autotune_picks_a_valid_shape_with_identical_results(T):
+    """The autotuner times candidate shapes; whatever it keeps must give the
+    same bits as the default shape (results do not depend on the launch)."""
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=128, ny=112)
+    ref = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], launch=T.make_launch(256, 0, 64, 4, T.ORDER_PIXEL))
+    out = T.alloc_outputs(cam["nx"] * cam["ny"])
+    best = T.tartarus_autotune(T.make_metric(w["a"]), [T.make_camera(cam)], T.make_disk(w["disk"]),
+                               T.make_solver(w["solver"]), out)
+    say("tuned", best.block_threads, best.blocks_per_cu, best.chunk, best.refill_min, best.order)
+    assert best.order in (T.ORDER_PIXEL, T.ORDER_COST)
+    assert best.block_threads in (64, 128, 256)
+    assert best.blocks_per_cu >= 0 and best.chunk >= 1 and 1 <= best.refill_min <= 64
+    tuned_out = T.to_numpy(out)
+    again = gpu_trace(T, w["a"], cam, w["disk"], w["solver"])        # default launch = the tuned one
+    for k in ref:
+        assert np.array_equal(ref[k], tuned_out[k]), k
+        assert np.array_equal(ref[k], again[k]), k
 
 # ------------------------------------------------------------------ tabulated metric
 def test_table_build_matches_oracle(T, orc):
