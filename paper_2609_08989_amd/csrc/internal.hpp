@@ -36,7 +36,26 @@ struct DevJob {
     unsigned int* remaining;        // serving: rays still running (may be null)
     int cancelled;                  // serving: drop the job's rays without writing outputs
     int pad1;
+    double* rec;                    // [ray_count][REC_DOUBLES] integrator -> finishing pass records
+    double event_tol;               // event location tolerance (affine parameter)
 };
+
+// Per-ray record the integrator leaves for the finishing pass (doubles).
+// Crossing slot k (k < 3) at REC_SLOT_LEN * k: r0, kr0, r1, kr1, th0, kth0, th1,
+// kth1, h, lam, cos(th0) of the step that crossed the equator on the disk (h = 0:
+// already located, r0 = radius, lam = affine parameter of the crossing).
+// Terminal step at REC_TERM: r, th, phi as (y0, dy0/dlam, y1, dy1/dlam) each,
+// then h, lam, target radius, cos(th0); for rays that end without a terminal
+// root (failed) only the three y0 are meaningful.  REC_CODE: terminal kind
+// (0 none, 1 horizon, 2 escape) + 4 if the equator was crossed in that step.
+// REC_INTS: int32 cls, n_hits, n_accept, n_reject, n_fp32, n_cross, order[3].
+constexpr int REC_SLOT_LEN = 11;
+constexpr int REC_TERM = 33;
+constexpr int REC_CODE = 49;
+constexpr int REC_HMAX = 50;
+constexpr int REC_HGATE = 51;
+constexpr int REC_INTS = 52;
+constexpr int REC_DOUBLES = 64;
 
 // Per-job constants computed on the device by the set-up kernel before a
 // trace: the observer's metric and ZAMO tetrad (Sec. 2.2), the horizon

@@ -30,7 +30,7 @@ using namespace tartarus;
 extern "C" hipError_t tartarus_launch_trace(int kind, int prec, const LaunchArgs* args, int grid, int block,
                                             hipStream_t stream);
 extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hipStream_t stream);
-extern "C" hipError_t tartarus_launch_shade(const LaunchArgs* args, int job0, int njobs, long long max_rays,
+extern "C" hipError_t tartarus_launch_finish(const LaunchArgs* args, int job0, int njobs, long long max_rays,
                                             hipStream_t stream);
 extern "C" hipError_t tartarus_occupancy(int kind, int prec, int block, int* blocks_per_cu);
 extern "C" hipError_t tartarus_launch_build_table(double a, int nr, int nth, double r_min, double r_max,
@@ -81,6 +81,8 @@ struct Slot {
     unsigned long long* head = nullptr;
     unsigned char* ord = nullptr;        // cost-ordered queue: order[n] u32, key[n] u8, count and cursor
     size_t ord_cap = 0;                  // bytes
+    double* rec = nullptr;               // per-ray records for the finishing pass
+    size_t rec_cap = 0;                  // rays
     hipEvent_t ev = nullptr;
     bool pending = false;
 };
@@ -221,7 +223,7 @@ int validate_all(const tartarus_metric* metric, const tartarus_camera* cams, int
 }
 
 void fill_job(DevJob& J, const tartarus_metric* m, const tartarus_camera& c, const tartarus_disk* d,
-              const tartarus_solver* s, const tartarus_outputs* o, long long begin, long long offset)
+              const tartarus_solver* s, const tartarus_outputs* o, long long begin, long long offset, double* rec)
 {
     std::memset(&J, 0, sizeof(J));
     J.ray_begin = begin;
@@ -254,6 +256,8 @@ void fill_job(DevJob& J, const tartarus_metric* m, const tartarus_camera& c, con
     J.n_fp32 = o->n_fp32 + offset;
     J.n_cross = o->n_cross + offset;
     J.remaining = nullptr;
+    J.rec = rec;
+    J.event_tol = s->event_tol;
 }
 
 void fill_args(LaunchArgs& A, const tartarus_metric* m, const tartarus_solver* s)
@@ -334,7 +338,16 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
     Slot* S = nullptr;
     if ((rc = take_slot(ncams, S))) return rc;
     const long long per = (long long)cams[0].nx * cams[0].ny;
-    for (int c = 0; c < ncams; ++c) fill_job(S->hjobs[c], metric, cams[c], disk, solver, out, c * per, c * per);
+    const size_t nrec = (size_t)per * ncams;
+    if (nrec > S->rec_cap) {
+        if (S->rec) (void)hipFree(S->rec);
+        S->rec = nullptr;
+        S->rec_cap = 0;
+        HIP_TRY(hipMalloc(&S->rec, nrec * REC_DOUBLES * sizeof(double)));
+        S->rec_cap = nrec;
+    }
+    for (int c = 0; c < ncams; ++c)
+        fill_job(S->hjobs[c], metric, cams[c], disk, solver, out, c * per, c * per, S->rec + (size_t)c * per * REC_DOUBLES);
     HIP_TRY(hipMemcpyAsync(S->djobs, S->hjobs, sizeof(DevJob) * ncams, hipMemcpyHostToDevice, stream));
     HIP_TRY(tartarus_launch_fill_u64(S->head, 0ull, 1, stream));
     LaunchArgs A;
@@ -371,7 +384,7 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
     }
     HIP_TRY(tartarus_launch_trace(kind, prec, &A, grid, L.block_threads, stream));
     for (int c0 = 0; c0 < ncams; c0 += 65535)
-        HIP_TRY(tartarus_launch_shade(&A, c0, std::min(65535, ncams - c0), per, stream));
+        HIP_TRY(tartarus_launch_finish(&A, c0, std::min(65535, ncams - c0), per, stream));
     HIP_TRY(hipEventRecord(S->ev, stream));
     S->pending = true;
     return TARTARUS_OK;
@@ -563,6 +576,7 @@ extern "C" int tartarus_shutdown(void)
         if (S.djc) (void)hipFree(S.djc);
         if (S.head) (void)hipFree(S.head);
         if (S.ord) (void)hipFree(S.ord);
+        if (S.rec) (void)hipFree(S.rec);
         if (S.ev) (void)hipEventDestroy(S.ev);
         S = Slot();
     }
@@ -596,8 +610,9 @@ int64_t now_ns()
 size_t output_bytes_per_ray()
 {
     // cls, n_hits, n_accept, n_reject, n_fp32, n_cross (int32); final_rtp[3], h_drift,
-    // h_gate, intensity (double); hit_r, hit_g, hit_flux, hit_lambda [3] (double); hit_order[3] (int32)
-    return 6 * 4 + 6 * 8 + 12 * 8 + 3 * 4;
+    // h_gate, intensity (double); hit_r, hit_g, hit_flux, hit_lambda [3] (double); hit_order[3] (int32);
+    // the ray's record for the finishing pass
+    return 6 * 4 + 6 * 8 + 12 * 8 + 3 * 4 + REC_DOUBLES * sizeof(double);
 }
 
 struct Request {
@@ -611,6 +626,7 @@ struct Request {
     int state = 0;          // 0 queued, 1 running, 2 done
     int entry = -1;
     long long ray_begin = 0;
+    double* rec = nullptr;  // device records of its rays while admitted
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     bool cancel_req = false, cancel_sent = false, cancel_acked = false;
     bool too_large = false;  // can never fit the budget next to the slot arena
@@ -730,6 +746,10 @@ void finish_request(Server& S, uint64_t ticket, Request& R)
         R.entry = -1;
         S.used_bytes -= R.bytes;
     }
+    if (R.rec) {
+        (void)hipFree(R.rec);
+        R.rec = nullptr;
+    }
     (void)ticket;
 }
 
@@ -754,6 +774,16 @@ int server_round(std::unique_lock<std::mutex>& lk)
         for (int e = 0; e < kMaxEntries; ++e)
             if (!S.entry_ticket[e]) { entry = e; break; }
         if (entry < 0 || S.used_bytes + R.bytes + S.arena_bytes > g_dev.budget) break;
+        if (hipMalloc(&R.rec, (size_t)R.nrays * REC_DOUBLES * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            R.rec = nullptr;
+            if (any_live(S)) break;   // retried once running requests have released memory
+            S.queue.pop_front();      // nothing else holds device memory: it never fits
+            R.too_large = true;
+            R.state = 2;
+            R.t_done = now_ns();
+            continue;
+        }
         S.queue.pop_front();
         R.entry = entry;
         R.ray_begin = S.next_ray;
@@ -762,7 +792,7 @@ int server_round(std::unique_lock<std::mutex>& lk)
         R.state = 1;
         R.t_admit = now_ns();
         S.entry_ticket[entry] = t;
-        fill_job(S.hjobs[entry], &R.metric, R.cam, &R.disk, &R.solver, &R.out, R.ray_begin, 0);
+        fill_job(S.hjobs[entry], &R.metric, R.cam, &R.disk, &R.solver, &R.out, R.ray_begin, 0, R.rec);
         S.hjobs[entry].remaining = S.dremaining + entry;
         S.hjobs[entry].cancelled = 0;
         S.hremaining[entry] = (unsigned int)R.nrays;
@@ -830,7 +860,7 @@ int server_round(std::unique_lock<std::mutex>& lk)
     std::vector<int> done;
     for (int e = 0; e < kMaxEntries; ++e)
         if (S.entry_ticket[e] && S.hremaining[e] == 0) done.push_back(e);
-    for (int e : done) HIP_TRY(tartarus_launch_shade(&A, e, 1, S.hjobs[e].ray_count, S.stream));
+    for (int e : done) HIP_TRY(tartarus_launch_finish(&A, e, 1, S.hjobs[e].ray_count, S.stream));
     if (!done.empty()) HIP_TRY(hipStreamSynchronize(S.stream));
 
     lk.lock();

@@ -59,6 +59,8 @@ struct Ray {
     int n_acc, n_rej, n_f32, n_cross, n_hits, rej_prev, max_hits, job;
     int k32;           // R.k was evaluated in FP32 (mixed precision)
     long long local;
+    double* rec;       // this ray's record for the finishing pass
+    double r_in, r_out;  // disk radii
 };
 
 template <int KIND>
@@ -262,45 +264,89 @@ __device__ void ray_init(Ray& R, long long gid, const LaunchArgs& A, const Metri
     R.max_hits = J.max_hits;
     R.job = jb;
     R.local = pix;
+    R.rec = J.rec + pix * REC_DOUBLES;
+    R.r_in = C.r_in;
+    R.r_out = J.disk_r_out;
 }
 
-__device__ void ray_finish(const Ray& R, const LaunchArgs& A, int cls, double fr, double fth, double fph)
+// The ray's counters and classification go to its record; the finishing pass
+// turns the record into outputs.  code: terminal kind | 4 * equator crossed in
+// the terminal step (REC_CODE).
+__device__ void ray_finish(const Ray& R, const LaunchArgs& A, int cls, int code)
 {
-    const DevJob& J = A.jobs[R.job];
-    const long long q = R.local;
-    J.cls[q] = cls;
-    J.n_hits[q] = R.n_hits;
-    J.final_rtp[3 * q + 0] = fr;
-    J.final_rtp[3 * q + 1] = fth;
-    J.final_rtp[3 * q + 2] = fph;
-    J.h_drift[q] = R.hmax;
-    J.h_gate[q] = R.hgate;
-    J.n_accept[q] = R.n_acc;
-    J.n_reject[q] = R.n_rej;
-    J.n_fp32[q] = R.n_f32;
-    J.n_cross[q] = R.n_cross;
-    for (int k = R.n_hits; k < 3; ++k) {
-        J.hit_r[3 * q + k] = 0.0;
-        J.hit_g[3 * q + k] = 0.0;
-        J.hit_flux[3 * q + k] = 0.0;
-        J.hit_lambda[3 * q + k] = 0.0;
-        J.hit_order[3 * q + k] = 0;
+    double* rec = R.rec;
+    rec[REC_CODE] = (double)code;
+    rec[REC_HMAX] = R.hmax;
+    rec[REC_HGATE] = R.hgate;
+    int* iv = reinterpret_cast<int*>(rec + REC_INTS);
+    iv[0] = cls;
+    iv[1] = R.n_hits;
+    iv[2] = R.n_acc;
+    iv[3] = R.n_rej;
+    iv[4] = R.n_f32;
+    iv[5] = R.n_cross;
+    if (A.slots) {
+        unsigned int* rem = A.jobs[R.job].remaining;
+        if (rem) atomicSub(rem, 1u);
     }
-    if (J.remaining) atomicSub(J.remaining, 1u);
 }
 
-// An equatorial crossing at radius rr: recorded when it lies on the disk and a
-// slot is free (shading happens in the shade pass).
-__device__ __forceinline__ void record_crossing(Ray& R, const LaunchArgs& A, double rr, double lam_hit)
+// A ray that ends where it stands (no terminal root to locate).
+__device__ void ray_fail(const Ray& R, const LaunchArgs& A)
+{
+    R.rec[REC_TERM + 0] = R.r;
+    R.rec[REC_TERM + 4] = R.th;
+    R.rec[REC_TERM + 8] = R.ph;
+    ray_finish(R, A, CLS_FAILED, 0);
+}
+
+// Equatorial crossing on the step's polar cubic (root of theta = pi/2, or of
+// cos(theta) = 0 where theta has left (-pi/2, 3pi/2)).
+__device__ __forceinline__ double equator_root(const Cubic& pth, double th0, double th1, double cth0, double h,
+                                               double tol)
+{
+    const bool wide = !(th0 > -M_PI_2 && th0 < 1.5 * M_PI && th1 > -M_PI_2 && th1 < 1.5 * M_PI);
+    return wide ? locate_equator_wide(pth, cth0 > 0.0, h, tol) : locate_root(pth, M_PI_2, cth0 < 0.0, h, tol);
+}
+
+// An equatorial crossing on a step that does not end the ray.  It counts, and
+// it takes the next free hit slot when it lies on the disk.  Where the step's
+// radial cubic stays inside the disk's radii (its Bernstein control points
+// bound it) the decision needs no root: the slot keeps the step and the
+// finishing pass locates the crossing.  Where it stays outside, nothing is
+// recorded.  Only steps that straddle an edge of the disk locate the root here.
+__device__ __forceinline__ void disk_crossing(Ray& R, double h, const Deriv<double>& y5, const Deriv<double>& k7,
+                                              double tol)
 {
     R.n_cross++;
     if (R.n_hits >= R.max_hits) return;
-    const DevJob& J = A.jobs[R.job];
-    if (!(rr >= A.jc[R.job].r_in && rr <= J.disk_r_out)) return;
-    const long long q = 3 * R.local + R.n_hits;
-    J.hit_r[q] = rr;
-    J.hit_lambda[q] = lam_hit;
-    J.hit_order[q] = R.n_cross;
+    const double b1 = fma(h * (1.0 / 3.0), R.k.r, R.r), b2 = fma(-h * (1.0 / 3.0), k7.r, y5.r);
+    const double lo = fmin(fmin(R.r, y5.r), fmin(b1, b2)), hi = fmax(fmax(R.r, y5.r), fmax(b1, b2));
+    constexpr double m = 1e-12;   // margin for rounding of the cubic evaluated at the root
+    if (hi < R.r_in * (1.0 - m) || lo > R.r_out * (1.0 + m)) return;
+    double* sl = R.rec + REC_SLOT_LEN * R.n_hits;
+    if (lo >= R.r_in * (1.0 + m) && hi <= R.r_out * (1.0 - m)) {
+        sl[0] = R.r;
+        sl[1] = R.k.r;
+        sl[2] = y5.r;
+        sl[3] = k7.r;
+        sl[4] = R.th;
+        sl[5] = R.k.th;
+        sl[6] = y5.th;
+        sl[7] = k7.th;
+        sl[8] = h;
+        sl[9] = R.lam;
+        sl[10] = R.cth;
+    } else {
+        const Cubic pth(R.th, R.k.th, y5.th, k7.th, h);
+        const double sd = equator_root(pth, R.th, y5.th, R.cth, h, tol);
+        const double rr = Cubic(R.r, R.k.r, y5.r, k7.r, h).at(sd);
+        if (!(rr >= R.r_in && rr <= R.r_out)) return;
+        sl[0] = rr;
+        sl[8] = 0.0;
+        sl[9] = fma(sd, h, R.lam);
+    }
+    reinterpret_cast<int*>(R.rec + REC_INTS)[6 + R.n_hits] = R.n_cross;
     R.n_hits++;
 }
 
@@ -457,7 +503,7 @@ template <int KIND, int PREC>
 __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
 {
     if ((long long)R.n_acc + R.n_rej >= A.max_steps) {
-        ray_finish(R, A, CLS_FAILED, R.r, R.th, R.ph);
+        ray_fail(R, A);
         return true;
     }
     const double h = R.h;
@@ -496,7 +542,7 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
         R.h = h * fac;
         R.rej_prev = 1;
         if (R.h < 1e-14 * fmax(1.0, fabs(R.lam))) {
-            ray_finish(R, A, CLS_FAILED, R.r, R.th, R.ph);
+            ray_fail(R, A);
             return true;
         }
         return false;
@@ -504,7 +550,7 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     R.n_acc++;
     if (!(isfinite(y5.t) && isfinite(y5.r) && isfinite(y5.th) && isfinite(y5.ph) && isfinite(y5.pr) &&
           isfinite(y5.pth))) {
-        ray_finish(R, A, CLS_FAILED, R.r, R.th, R.ph);
+        ray_fail(R, A);
         return true;
     }
 
@@ -520,36 +566,30 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     const bool hz = (R.r - r_stop > 0.0) && (y5.r - r_stop <= 0.0);
     const bool es = (R.r - r_esc < 0.0) && (y5.r - r_esc >= 0.0);
     const bool dk = R.max_hits > 0 && ((R.cth > 0.0 && c5 <= 0.0) || (R.cth < 0.0 && c5 >= 0.0));
-    if (hz | es | dk) {
-        const double tol = 0.125 * A.event_tol;
-        const Cubic pr_(R.r, R.k.r, y5.r, k7.r, h);
-        double s_term = 2.0, s_disk = 2.0;
-        int term = 0;
-        // at most one of the two radial events can bracket a root in one step
-        if (hz) {
-            s_term = locate_root(pr_, r_stop, true, h, tol);
-            term = 1;
-        } else if (es) {
-            s_term = locate_root(pr_, r_esc, false, h, tol);
-            term = 2;
-        }
-        if (dk) {
-            const Cubic pth_(R.th, R.k.th, y5.th, k7.th, h);
-            const bool wide = !(R.th > -M_PI_2 && R.th < 1.5 * M_PI && y5.th > -M_PI_2 && y5.th < 1.5 * M_PI);
-            s_disk = wide ? locate_equator_wide(pth_, R.cth > 0.0, h, tol)
-                          : locate_root(pth_, M_PI_2, R.cth < 0.0, h, tol);
-        }
-        // events in root order; a disk crossing at or before the terminal root
-        // is recorded, one after it is dropped
-        if (dk && s_disk <= s_term) record_crossing(R, A, pr_.at(s_disk), fma(s_disk, h, R.lam));
-        if (term) {
-            const Cubic pth_(R.th, R.k.th, y5.th, k7.th, h);
-            const Cubic pph_(R.ph, R.k.ph, y5.ph, k7.ph, h);
-            ray_finish(R, A, term == 1 ? CLS_CAPTURED : CLS_ESCAPED, pr_.at(s_term), pth_.at(s_term),
-                       pph_.at(s_term));
-            return true;
-        }
+    if (hz | es) {
+        // terminal step: the finishing pass locates the root (and a crossing
+        // of the equator before it) on the step's cubics
+        double* t = R.rec + REC_TERM;
+        t[0] = R.r;
+        t[1] = R.k.r;
+        t[2] = y5.r;
+        t[3] = k7.r;
+        t[4] = R.th;
+        t[5] = R.k.th;
+        t[6] = y5.th;
+        t[7] = k7.th;
+        t[8] = R.ph;
+        t[9] = R.k.ph;
+        t[10] = y5.ph;
+        t[11] = k7.ph;
+        t[12] = h;
+        t[13] = R.lam;
+        t[14] = hz ? r_stop : r_esc;   // at most one radial event brackets a root in one step
+        t[15] = R.cth;
+        ray_finish(R, A, hz ? CLS_CAPTURED : CLS_ESCAPED, (hz ? 1 : 2) | (dk ? 4 : 0));
+        return true;
     }
+    if (dk) disk_crossing(R, h, y5, k7, 0.125 * A.event_tol);
 
     R.lam += h;
     R.t = y5.t;
@@ -683,10 +723,14 @@ trace_persistent(LaunchArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// shading: g and g^4 F(r) of the recorded crossings, pixel intensity
+// finishing pass: event roots, outputs, and shading (g and g^4 F(r))
 // ---------------------------------------------------------------------------
-// blockIdx.y selects the job (job0 + blockIdx.y); x covers its rays.
-__global__ void shade_kernel(const DevJob* jobs, const JobConst* jc, int job0)
+// One thread per ray.  Locates the crossings and the terminal root the
+// integrator left in the ray's record (same cubics and root finders as on the
+// integrator side, so the results do not depend on where a root was found),
+// writes every output of the ray, then shades its disk hits with Eqs. (11)
+// and (15).  blockIdx.y selects the job (job0 + blockIdx.y); x covers its rays.
+__global__ void finish_kernel(const DevJob* jobs, const JobConst* jc, int job0)
 {
     const int jb = job0 + blockIdx.y;
     const DevJob& J = jobs[jb];
@@ -694,22 +738,92 @@ __global__ void shade_kernel(const DevJob* jobs, const JobConst* jc, int job0)
     if (q >= J.ray_count) return;
     if (J.cancelled) return;
     const JobConst& C = jc[jb];
-    const int n = J.n_hits[q];
+    const double* rec = J.rec + q * REC_DOUBLES;
+    const int* iv = reinterpret_cast<const int*>(rec + REC_INTS);
+    const double tol = 0.125 * J.event_tol;
+    int n = iv[1];
+    int n_cross = iv[5];
+    double hr[3] = {0.0, 0.0, 0.0}, hl[3] = {0.0, 0.0, 0.0};
+    int ho[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= n) break;
+        const double* sl = rec + REC_SLOT_LEN * k;
+        if (sl[8] > 0.0) {
+            const double h = sl[8];
+            const Cubic pth(sl[4], sl[5], sl[6], sl[7], h);
+            const double sd = equator_root(pth, sl[4], sl[6], sl[10], h, tol);
+            hr[k] = Cubic(sl[0], sl[1], sl[2], sl[3], h).at(sd);
+            hl[k] = fma(sd, h, sl[9]);
+        } else {
+            hr[k] = sl[0];
+            hl[k] = sl[9];
+        }
+        ho[k] = iv[6 + k];
+    }
+    const double* t = rec + REC_TERM;
+    const int code = (int)rec[REC_CODE];
+    double fr = t[0], fth = t[4], fph = t[8];
+    if (code & 3) {
+        const double h = t[12];
+        const Cubic pr(t[0], t[1], t[2], t[3], h);
+        const Cubic pth(t[4], t[5], t[6], t[7], h);
+        const double s_term = locate_root(pr, t[14], (code & 3) == 1, h, tol);
+        if (code & 4) {
+            // a crossing at or before the terminal root counts, one after it does not
+            const double s_disk = equator_root(pth, t[4], t[6], t[15], h, tol);
+            if (s_disk <= s_term) {
+                n_cross++;
+                const double rr = pr.at(s_disk);
+                if (n < J.max_hits && rr >= C.r_in && rr <= J.disk_r_out) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        if (k == n) {
+                            hr[k] = rr;
+                            hl[k] = fma(s_disk, h, t[13]);
+                            ho[k] = n_cross;
+                        }
+                    n++;
+                }
+            }
+        }
+        fr = pr.at(s_term);
+        fth = pth.at(s_term);
+        fph = Cubic(t[8], t[9], t[10], t[11], h).at(s_term);
+    }
+    J.cls[q] = iv[0];
+    J.n_hits[q] = n;
+    J.final_rtp[3 * q + 0] = fr;
+    J.final_rtp[3 * q + 1] = fth;
+    J.final_rtp[3 * q + 2] = fph;
+    J.h_drift[q] = rec[REC_HMAX];
+    J.h_gate[q] = rec[REC_HGATE];
+    J.n_accept[q] = iv[2];
+    J.n_reject[q] = iv[3];
+    J.n_fp32[q] = iv[4];
+    J.n_cross[q] = n_cross;
     double inten = 0.0;
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
     if (n > 0) {
-        double al, be, p[4];
+        double al, be;
         pixel_coords(J, q, al, be);
         pixel_momentum(C, J.r_obs, al, be, p);
-        for (int k = 0; k < n; ++k) {
-            const double rr = J.hit_r[3 * q + k];
-            const double g = redshift(J.a, rr, p[0], p[3]);
-            const double F = nt_flux_pre(J.a, C.x0, C.xi, C.coef, rr);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double g = 0.0, flux = 0.0;
+        if (k < n) {
+            g = redshift(J.a, hr[k], p[0], p[3]);
+            const double F = nt_flux_pre(J.a, C.x0, C.xi, C.coef, hr[k]);
             const double g2 = g * g;
-            const double flux = g2 * g2 * F;
-            J.hit_g[3 * q + k] = g;
-            J.hit_flux[3 * q + k] = flux;
+            flux = g2 * g2 * F;
             inten += flux;
         }
+        J.hit_r[3 * q + k] = hr[k];
+        J.hit_g[3 * q + k] = g;
+        J.hit_flux[3 * q + k] = flux;
+        J.hit_lambda[3 * q + k] = hl[k];
+        J.hit_order[3 * q + k] = ho[k];
     }
     J.intensity[q] = inten;
 }
@@ -834,13 +948,13 @@ extern "C" hipError_t tartarus_launch_trace(int kind, int prec, const LaunchArgs
 }
 
 // Shade jobs [job0, job0 + njobs), each with at most max_rays rays.
-extern "C" hipError_t tartarus_launch_shade(const LaunchArgs* args, int job0, int njobs, long long max_rays,
+extern "C" hipError_t tartarus_launch_finish(const LaunchArgs* args, int job0, int njobs, long long max_rays,
                                             hipStream_t stream)
 {
     if (njobs <= 0 || max_rays <= 0) return hipSuccess;
     const long long bx = (max_rays + 255) / 256;
     if (bx > 0x7fffffffll || njobs > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(shade_kernel, dim3((unsigned)bx, (unsigned)njobs), dim3(256), 0, stream, args->jobs, args->jc,
+    hipLaunchKernelGGL(finish_kernel, dim3((unsigned)bx, (unsigned)njobs), dim3(256), 0, stream, args->jobs, args->jc,
                        job0);
     return hipGetLastError();
 }

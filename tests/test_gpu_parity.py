@@ -171,7 +171,7 @@ def test_autotune_picks_a_valid_shape_with_identical_results(T):
     best = T.tartarus_autotune(T.make_metric(w["a"]), [T.make_camera(cam)], T.make_disk(w["disk"]),
                                T.make_solver(w["solver"]), out)
     say("tuned", best.block_threads, best.blocks_per_cu, best.chunk, best.refill_min, best.order)
-    assert best.order in (T.ORDER_PIXEL, T.ORDER_COST)
+    assert best.order in (T.ORDER_DEFAULT, T.ORDER_PIXEL, T.ORDER_COST)
     assert best.block_threads in (64, 128, 256)
     assert best.blocks_per_cu >= 0 and best.chunk >= 1 and 1 <= best.refill_min <= 64
     tuned_out = T.to_numpy(out)
