@@ -4,10 +4,12 @@
 //
 // sincos64: Cody & Waite argument reduction x = k pi/2 + r with pi/2 split in
 // three doubles (each product k * P_i is fused, so the reduction is exact to
-// well below an ulp of r for |k| < 2^20), then the Taylor series of sin and
-// cos on |r| <= pi/4 truncated after r^17 / 17! and r^16 / 16! (truncation
-// error below 7e-17 relative), and the quadrant swap.  Valid for |x| < 1e6;
-// the polar angle of a ray stays within a few pi.
+// well below an ulp of r for |k| < 2^20), then polynomials for sin r and cos r
+// on |r| <= pi/4, and the quadrant swap.  The polynomials are the Taylor
+// series economized on that interval (Chebyshev re-expansion, cut at degree
+// 13 for sin and 14 for cos, truncation error below 4e-18; sincos_coeffs.py
+// derives the coefficients).  Valid for |x| < 1e6; the polar angle of a ray
+// stays within a few pi.
 #pragma once
 
 #include <cmath>
@@ -33,25 +35,22 @@ TT_HD inline void sincos64(double x, double* sp, double* cp)
     r = std::fma(-k, kPio2Mid, r);
     r = std::fma(-k, kPio2Lo, r);
     const double r2 = r * r;
-    // sin r = r + r^3 * (-1/3! + r^2 (1/5! - r^2 (1/7! - ...)))
-    double ps = 2.8114572543455206e-15;                 //  1/17!
-    ps = std::fma(ps, r2, -7.647163731819816e-13);      // -1/15!
-    ps = std::fma(ps, r2, 1.6059043836821613e-10);      //  1/13!
-    ps = std::fma(ps, r2, -2.505210838544172e-08);      // -1/11!
-    ps = std::fma(ps, r2, 2.7557319223985893e-06);      //  1/9!
-    ps = std::fma(ps, r2, -0.0001984126984126984);      // -1/7!
-    ps = std::fma(ps, r2, 0.008333333333333333);        //  1/5!
-    ps = std::fma(ps, r2, -0.16666666666666666);        // -1/3!
+    // sin r = r + r^3 (s1 + r^2 (s2 + ... + r^2 s6))
+    double ps = 1.5894740706160615e-10;
+    ps = std::fma(ps, r2, -2.5050717053109253e-08);
+    ps = std::fma(ps, r2, 2.7557313376976021e-06);
+    ps = std::fma(ps, r2, -0.0001984126982865223);
+    ps = std::fma(ps, r2, 0.0083333333333203662);
+    ps = std::fma(ps, r2, -0.16666666666666616);
     const double sr = std::fma(ps * r2, r, r);
-    // cos r = 1 + r^2 * (-1/2 + r^2 (1/4! - ...))
-    double pc = 4.779477332387385e-14;                  //  1/16!
-    pc = std::fma(pc, r2, -1.1470745597729725e-11);     // -1/14!
-    pc = std::fma(pc, r2, 2.08767569878681e-09);        //  1/12!
-    pc = std::fma(pc, r2, -2.755731922398589e-07);      // -1/10!
-    pc = std::fma(pc, r2, 2.48015873015873e-05);        //  1/8!
-    pc = std::fma(pc, r2, -0.001388888888888889);       // -1/6!
-    pc = std::fma(pc, r2, 0.041666666666666664);        //  1/4!
-    pc = std::fma(pc, r2, -0.5);                        // -1/2
+    // cos r = 1 + r^2 (c1 + r^2 (c2 + ... + r^2 c7))
+    double pc = -1.1353381481384318e-11;
+    pc = std::fma(pc, r2, 2.0875582423297387e-09);
+    pc = std::fma(pc, r2, -2.7557313098175798e-07);
+    pc = std::fma(pc, r2, 2.4801587283882876e-05);
+    pc = std::fma(pc, r2, -0.0013888888888861099);
+    pc = std::fma(pc, r2, 0.041666666666666449);
+    pc = std::fma(pc, r2, -0.5);
     const double cr = std::fma(pc, r2, 1.0);
     const int q = ((int)(long long)k) & 3;
     const double s = (q & 1) ? cr : sr;

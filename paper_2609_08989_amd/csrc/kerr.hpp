@@ -46,18 +46,21 @@ __device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double
     const double W = fma(a * s2, pt, pph);
     const double Ws = W * is2;
     const double PiD = P * iD;
-    const double K = fma(del * pr, pr, fma(pth, pth, fma(W, Ws, -P * PiD)));
-    d.r = del * pr * iS;
+    const double dpr = del * pr;
+    const double K = fma(dpr, pr, fma(pth, pth, fma(W, Ws, -P * PiD)));
+    const double iSK = iS * K;   // K / Sigma = 2 H
+    d.r = dpr * iS;
     d.th = pth * iS;
     d.ph = fma(-a, PiD, Ws) * iS;
     d.t = fma(a, W, -ra * PiD) * iS;
-    const double dKr = fma(2.0 * (r - 1.0), fma(pr, pr, PiD * PiD), -4.0 * r * pt * PiD);
-    d.pr = -0.5 * iS * fma(-2.0 * r * iS, K, dKr);
+    // dp_r = -(1/2) d(K / Sigma)/dr with dK/dr = 2 (r - 1)(p_r^2 + (P/Delta)^2) - 4 r p_t P/Delta
+    // and dSigma/dr = 2 r
+    d.pr = iS * fma(r, fma(2.0 * pt, PiD, iSK), (1.0 - r) * fma(pr, pr, PiD * PiD));
+    // dp_theta = -(1/2) d(K / Sigma)/dtheta with dK/dtheta = 2 sin cos (a^2 p_t^2 - (p_phi / sin^2)^2)
+    // and dSigma/dtheta = -2 a^2 sin cos
     const double q = pph * is2;
-    const double sc = s * c;
-    const double dKth = 2.0 * sc * fma(a2 * pt, pt, -q * q);
-    d.pth = -0.5 * iS * fma(2.0 * a2 * sc * iS, K, dKth);
-    H = 0.5 * K * iS;
+    d.pth = -(iS * (s * c)) * fma(a2, fma(pt, pt, iSK), -(q * q));
+    H = 0.5 * iSK;
     cth = c;
 }
 

@@ -637,12 +637,13 @@ __device__ __forceinline__ bool drop_if_cancelled(const Ray& R, const LaunchArgs
     return true;
 }
 
-// Occupancy target per instantiation: the analytic FP64 integrator fits 168
-// VGPRs (3 waves per SIMD) without spilling in its loop; the mixed and
-// tabulated ones need more registers and run at 2.
+// Occupancy target: up to 256 VGPRs, at most 2 waves per SIMD.  One wave per
+// SIMD is usually fastest once the event roots are left to the finishing pass
+// (a lone wavefront keeps the long rays' critical path short); a second gives
+// the short rays more throughput.  The autotuner picks between the two.
 template <int KIND, int PREC>
 struct WavesPerEU {
-    static constexpr int value = (KIND == 0 && PREC == 0) ? 3 : 2;
+    static constexpr int value = 2;
 };
 
 template <int KIND, int PREC>
