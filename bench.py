@@ -21,6 +21,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -56,6 +58,32 @@ def log(*a):
 
 
 SHAPE_KEYS = ("block_threads", "blocks_per_cu", "chunk", "refill_min", "order")
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "trace_persistent_fp64_kerr09_512.traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the device sources; HBM traffic measured for other sources is stale."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "paper_2609_08989_amd", "csrc", "*.h*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(launch_shape):
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), if they were taken on these
+    kernel sources with this launch shape; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("source_sha256") != kernel_source_hash() or t.get("launch") != launch_shape:
+        return None
+    return float(t["fetch_bytes"] + t["write_bytes"])
 
 
 def shape(L):
@@ -209,7 +237,8 @@ def main():
                    "gate_h_max": h_gate_max, "gate_holds": bool(h_gate_max <= 1e-8),
                    "failed_rays": int((o["cls"] == 2).sum()), "attempts_per_ray": float(att.mean())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(",".join(str(v) for v in tuned.get("fp64", []))),
                      "kernel": "trace_persistent<0,0> (analytic Kerr, FP64)",
                      "kernel_ms": kern_ms, "flop_per_launch": flops,
                      "flop_per_attempt": FLOP_ATTEMPT},
