@@ -59,6 +59,35 @@ TT_HD inline void sincos64(double x, double* sp, double* cp)
     *cp = ((q + 1) & 2) ? -c : c;
 }
 
+// sincos32: the single-precision counterpart for the FP32 far-field stages.
+// Cody & Waite reduction with pi/2 in three floats (fused products), then the
+// Taylor series economized on |r| <= pi/4 to degree 7 (sin) and 8 (cos)
+// (truncation below 3e-9 and 5e-11, under 0.05 ulp of float; sincos_coeffs.py
+// with the single-precision degrees).  Valid for |x| < 1e4, far beyond any
+// polar angle a ray reaches; no large-argument branch.
+TT_HD inline void sincos32(float x, float* sp, float* cp)
+{
+    const float k = std::rint(x * 0.63661975f);
+    float r = std::fma(-k, 1.57079637f, x);
+    r = std::fma(-k, -4.37113883e-08f, r);
+    r = std::fma(-k, -1.77635684e-15f, r);
+    const float r2 = r * r;
+    float ps = -0.000195039582f;
+    ps = std::fma(ps, r2, 0.00833203644f);
+    ps = std::fma(ps, r2, -0.166666508f);
+    const float sr = std::fma(ps * r2, r, r);
+    float pc = 2.43798731e-05f;
+    pc = std::fma(pc, r2, -0.00138866180f);
+    pc = std::fma(pc, r2, 0.0416666158f);
+    pc = std::fma(pc, r2, -0.5f);
+    const float cr = std::fma(pc, r2, 1.0f);
+    const int q = ((int)k) & 3;
+    const float s = (q & 1) ? cr : sr;
+    const float c = (q & 1) ? sr : cr;
+    *sp = (q & 2) ? -s : s;
+    *cp = ((q + 1) & 2) ? -c : c;
+}
+
 #if defined(__HIPCC__)
 // 1/x from the hardware reciprocal estimate refined by two Newton-Raphson
 // steps (r <- r + r (1 - x r)); within an ulp or two of the rounded quotient.

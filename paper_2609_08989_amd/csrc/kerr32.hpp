@@ -28,7 +28,7 @@ __device__ __forceinline__ void kerr_rhs32(float a, float r, float th, float pr,
                                            Deriv<float>& d)
 {
     float s, c;
-    sincosf(th, &s, &c);
+    sincos32(th, &s, &c);
     const float a2 = a * a;
     const float r2 = r * r;
     const float s2 = s * s;

@@ -354,10 +354,18 @@ __device__ __forceinline__ void disk_crossing(Ray& R, double h, const Deriv<doub
 // The regime is decided per ray from its own state only (never from its
 // wavefront), so a ray's arithmetic is the same in any batch.  FP32 stages are
 // used where r >= r_switch_factor * r_+ at the start of the step, away from
-// radial and polar turning points.
+// radial and polar turning points, away from the polar axis, and not right
+// after a rejected attempt.  Near the axis sin(theta) is small and p_phi /
+// sin^2(theta) large, and theta rounded to FP32 leaves sin^2(theta) with a
+// relative error of order 1e-7 / sin(theta): the FP32 error estimate of p_theta
+// then sits above the tolerance and the step collapses (rays of zero angular
+// momentum cross the axis; |cos(theta)| <= 0.995 keeps them in FP64 there).  A
+// rejection is retried with FP64 stages instead of shrinking the step on FP32
+// rounding noise.
 __device__ __forceinline__ bool far_field(const Ray& R, const LaunchArgs& A)
 {
-    return R.r >= A.r_switch_factor * R.rp && fabs(R.pr) >= (double)R.guard_r && fabs(R.pth) >= (double)R.guard_th;
+    return !R.rej_prev && R.r >= A.r_switch_factor * R.rp && R.cth * R.cth <= 0.99 &&
+           fabs(R.pr) >= (double)R.guard_r && fabs(R.pth) >= (double)R.guard_th;
 }
 
 // One attempted DP45 step whose six new stage evaluations run in FP32 (on-shell

@@ -15,6 +15,9 @@ SRC = r"""
 extern "C" void run(const double* x, double* s, double* c, long n) {
     for (long i = 0; i < n; ++i) tartarus::sincos64(x[i], s + i, c + i);
 }
+extern "C" void run32(const float* x, float* s, float* c, long n) {
+    for (long i = 0; i < n; ++i) tartarus::sincos32(x[i], s + i, c + i);
+}
 """
 
 
@@ -29,6 +32,8 @@ def lib():
     L = C.CDLL(so)
     dp = C.POINTER(C.c_double)
     L.run.argtypes = [dp, dp, dp, C.c_long]
+    fp = C.POINTER(C.c_float)
+    L.run32.argtypes = [fp, fp, fp, C.c_long]
     return L
 
 
@@ -64,3 +69,19 @@ def test_equator_sign(lib):
     x = np.pi / 2 + 1e-15 + np.arange(0, 50) * 1e-16
     s, c = run(lib, x)
     assert np.all(c < 0)
+
+
+def test_sincos32_accuracy(lib):
+    """Single-precision sin/cos of the FP32 far-field stages: within 2 ulp of
+    float for |sin|, |cos| > 1e-3 (absolute 1.2e-7 near the zeros)."""
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.uniform(-10, 10, 200000), np.linspace(-7, 7, 20001)]).astype(np.float32)
+    s, c = np.zeros_like(x), np.zeros_like(x)
+    fp = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
+    lib.run32(fp(x), fp(s), fp(c), len(x))
+    xd = x.astype(np.float64)
+    es, ec = np.sin(xd), np.cos(xd)
+    us = np.abs(s - es) / np.spacing(np.maximum(np.abs(es), 1e-30).astype(np.float32))
+    uc = np.abs(c - ec) / np.spacing(np.maximum(np.abs(ec), 1e-30).astype(np.float32))
+    assert us[np.abs(es) > 1e-3].max() <= 2.0 and uc[np.abs(ec) > 1e-3].max() <= 2.0
+    assert np.abs(s - es).max() < 1.2e-7 and np.abs(c - ec).max() < 1.2e-7
