@@ -169,7 +169,10 @@ typedef struct {
  * not gfx950. */
 int tartarus_init(int device, size_t hbm_budget_bytes);
 
-/* Release the library's device memory and stop the serving thread. */
+/* Release the library's device memory and stop the serving thread.  Call it
+ * before the process exits (and before the HIP runtime is torn down) when
+ * tartarus_submit has been used: a serving thread still running at exit keeps
+ * the device busy.  The Python binding registers it with atexit. */
 int tartarus_shutdown(void);
 
 /* Check the arguments of a trace without touching the device (same checks as

@@ -102,6 +102,8 @@ struct LaunchArgs {
     int pad2;
     // queue position -> ray index (relative to first_ray); null: identity
     const unsigned int* order;
+    // serving: rays still to finish, per job-table entry (null: not counted)
+    unsigned int* remaining;
 };
 
 constexpr int SLOT_DOUBLES = 32;

@@ -627,6 +627,7 @@ struct Request {
     int entry = -1;
     long long ray_begin = 0;
     double* rec = nullptr;  // device records of its rays while admitted
+    long long rec_rays = 0; // capacity of rec in rays
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     bool cancel_req = false, cancel_sent = false, cancel_acked = false;
     bool too_large = false;  // can never fit the budget next to the slot arena
@@ -666,9 +667,53 @@ struct Server {
     long long nslots = 0;
     int grid = 0, block = 0;
     size_t arena_bytes = 0;
+    // freed per-request record buffers kept for reuse (hipFree would
+    // synchronize the device between epochs): size in rays -> buffers
+    std::multimap<long long, double*> rec_pool;
+    size_t rec_pool_bytes = 0;
     std::string dev_error;
 };
 Server g_srv;
+
+// A record buffer for n rays: the smallest pooled one that fits, else a new one.
+double* rec_take(Server& S, long long n, long long& cap)
+{
+    auto it = S.rec_pool.lower_bound(n);
+    if (it != S.rec_pool.end() && it->first <= 4 * n) {
+        double* p = it->second;
+        cap = it->first;
+        S.rec_pool_bytes -= (size_t)it->first * REC_DOUBLES * sizeof(double);
+        S.rec_pool.erase(it);
+        return p;
+    }
+    double* p = nullptr;
+    if (hipMalloc(&p, (size_t)n * REC_DOUBLES * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        // release the pool and try once more
+        for (auto& kv : S.rec_pool) (void)hipFree(kv.second);
+        S.rec_pool.clear();
+        S.rec_pool_bytes = 0;
+        if (hipMalloc(&p, (size_t)n * REC_DOUBLES * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    cap = n;
+    return p;
+}
+
+// Return a buffer of n rays to the pool (kept while the pool stays under a
+// quarter of the HBM budget, else freed).
+void rec_give(Server& S, double* p, long long n)
+{
+    const size_t b = (size_t)n * REC_DOUBLES * sizeof(double);
+    if (S.rec_pool_bytes + b <= g_dev.budget / 4) {
+        S.rec_pool.emplace(n, p);
+        S.rec_pool_bytes += b;
+    } else {
+        (void)hipFree(p);
+    }
+}
 
 int server_alloc(int prec)
 {
@@ -720,6 +765,9 @@ void server_free()
     (void)hipHostFree(S.hdir_job);
     (void)hipFree(S.slots);
     (void)hipFree(S.slot_live);
+    for (auto& kv : S.rec_pool) (void)hipFree(kv.second);
+    S.rec_pool.clear();
+    S.rec_pool_bytes = 0;
     (void)hipFree(S.dhead);
     (void)hipHostFree(S.hhead);
     if (S.stream) (void)hipStreamDestroy(S.stream);
@@ -747,7 +795,7 @@ void finish_request(Server& S, uint64_t ticket, Request& R)
         S.used_bytes -= R.bytes;
     }
     if (R.rec) {
-        (void)hipFree(R.rec);
+        rec_give(S, R.rec, R.rec_rays);
         R.rec = nullptr;
     }
     (void)ticket;
@@ -774,9 +822,8 @@ int server_round(std::unique_lock<std::mutex>& lk)
         for (int e = 0; e < kMaxEntries; ++e)
             if (!S.entry_ticket[e]) { entry = e; break; }
         if (entry < 0 || S.used_bytes + R.bytes + S.arena_bytes > g_dev.budget) break;
-        if (hipMalloc(&R.rec, (size_t)R.nrays * REC_DOUBLES * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            R.rec = nullptr;
+        R.rec = rec_take(S, R.nrays, R.rec_rays);
+        if (!R.rec) {
             if (any_live(S)) break;   // retried once running requests have released memory
             S.queue.pop_front();      // nothing else holds device memory: it never fits
             R.too_large = true;
@@ -839,17 +886,22 @@ int server_round(std::unique_lock<std::mutex>& lk)
     A.jobs = S.djobs;
     A.jc = S.djc;
     A.njobs = kMaxEntries;
-    A.chunk = 64;
-    A.refill_min = 16;
+    A.chunk = 1;
+    A.refill_min = 4;
     A.first_ray = first;
     A.total_rays = total;
     A.head = S.dhead;
     A.slots = S.slots;
     A.slot_live = S.slot_live;
     A.step_budget = kEpochAttempts;
+    if (const char* e = std::getenv("TARTARUS_EPOCH_ATTEMPTS")) {   // experiment override
+        const long long v = std::atoll(e);
+        if (v > 0) A.step_budget = v;
+    }
     A.dir_begin = S.ddir_begin;
     A.dir_job = S.ddir_job;
     A.ndir = nd;
+    A.remaining = S.dremaining;
     if (!fresh.empty()) HIP_TRY(tartarus_launch_setup(TARTARUS_METRIC_KERR, &A, S.stream));
     HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, sv.precision, &A, S.grid, S.block, S.stream));
     HIP_TRY(hipMemcpyAsync(S.hremaining, S.dremaining, sizeof(unsigned int) * kMaxEntries, hipMemcpyDeviceToHost,
@@ -1033,6 +1085,12 @@ void server_stop()
     }
     if (S.th.joinable()) S.th.join();
     std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stream) (void)hipStreamSynchronize(S.stream);
+    for (auto& kv : S.reqs)
+        if (kv.second.rec) {
+            (void)hipFree(kv.second.rec);
+            kv.second.rec = nullptr;
+        }
     if (S.dev_ready) server_free();
     S.queue.clear();
     S.reqs.clear();

@@ -202,8 +202,31 @@ __device__ __noinline__ double locate_equator_wide(const Cubic& p, bool north_st
     return 0.5 * (lo + hi);
 }
 
-__device__ __forceinline__ int find_job(const LaunchArgs& A, long long gid)
+// Job of global ray index gid: binary search over the first ray of each job
+// (serving: over the directory of live entries).  The persistent kernel keeps a
+// copy of the search keys in LDS when they fit (kLdsJobs), so a refill does not
+// wait on a chain of dependent global loads.
+constexpr int kLdsJobs = 1024;
+
+struct JobDir {
+    const long long* begin;   // LDS copy, or null: search the global tables
+    const int* job;
+    int n;
+};
+
+__device__ __forceinline__ int find_job(const LaunchArgs& A, const JobDir& D, long long gid)
 {
+    if (D.begin) {
+        int lo = 0, hi = D.n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (D.begin[mid] <= gid)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return D.job[lo];
+    }
     if (A.dir_begin) {
         int lo = 0, hi = A.ndir - 1;
         while (lo < hi) {
@@ -229,10 +252,12 @@ __device__ __forceinline__ int find_job(const LaunchArgs& A, long long gid)
 // ---------------------------------------------------------------------------
 // one ray
 // ---------------------------------------------------------------------------
+// Returns false when the ray's job has been cancelled (serving): then the ray
+// is not traced.
 template <int KIND>
-__device__ void ray_init(Ray& R, long long gid, const LaunchArgs& A, const MetricOps<KIND>& M)
+__device__ bool ray_init(Ray& R, long long gid, const LaunchArgs& A, const JobDir& D, const MetricOps<KIND>& M)
 {
-    const int jb = find_job(A, gid);
+    const int jb = find_job(A, D, gid);
     const DevJob& J = A.jobs[jb];
     const JobConst& C = A.jc[jb];
     const long long pix = gid - J.ray_begin;
@@ -267,6 +292,7 @@ __device__ void ray_init(Ray& R, long long gid, const LaunchArgs& A, const Metri
     R.rec = J.rec + pix * REC_DOUBLES;
     R.r_in = C.r_in;
     R.r_out = J.disk_r_out;
+    return !J.cancelled;
 }
 
 // The ray's counters and classification go to its record; the finishing pass
@@ -285,10 +311,7 @@ __device__ void ray_finish(const Ray& R, const LaunchArgs& A, int cls, int code)
     iv[3] = R.n_rej;
     iv[4] = R.n_f32;
     iv[5] = R.n_cross;
-    if (A.slots) {
-        unsigned int* rem = A.jobs[R.job].remaining;
-        if (rem) atomicSub(rem, 1u);
-    }
+    (void)A;
 }
 
 // A ray that ends where it stands (no terminal root to locate).
@@ -636,13 +659,22 @@ __device__ __forceinline__ void unpark(Ray& R, const double* slot)
     for (int i = 0; i < (int)(sizeof(Ray) / sizeof(double)); ++i) dst[i] = slot[i];
 }
 
-// A ray of a cancelled job terminates without writing its outputs.
-__device__ __forceinline__ bool drop_if_cancelled(const Ray& R, const LaunchArgs& A)
+// Serving: the rays of each job still to finish are counted down on the
+// device.  Lanes whose ray ended this iteration (finished, failed or dropped
+// with a cancelled job) carry its job in `done`; one atomic per job and
+// wavefront iteration subtracts them, instead of one per ray on a single
+// counter.
+__device__ __forceinline__ void count_done(const LaunchArgs& A, int& done)
 {
-    const DevJob& J = A.jobs[R.job];
-    if (!J.cancelled) return false;
-    if (J.remaining) atomicSub(J.remaining, 1u);
-    return true;
+    unsigned long long m = __ballot(done >= 0);
+    while (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        const int j = __shfl(done, leader);
+        const unsigned long long same = __ballot(done == j);
+        if ((int)__lane_id() == leader) atomicSub(A.remaining + j, (unsigned int)__popcll(same));
+        if (done == j) done = -1;
+        m &= ~same;
+    }
 }
 
 // Occupancy target: up to 256 VGPRs, at most 2 waves per SIMD.  One wave per
@@ -660,17 +692,36 @@ trace_persistent(LaunchArgs A)
 {
     MetricOps<KIND> M;
     if (KIND == 1) M.T = make_table_view(A.table, A.nr, A.nth, A.tab_r_min, A.tab_r_max);
+    // job directory in LDS
+    __shared__ long long s_begin[kLdsJobs];
+    __shared__ int s_job[kLdsJobs];
+    JobDir D;
+    D.n = A.dir_begin ? A.ndir : A.njobs;
+    D.begin = nullptr;
+    D.job = nullptr;
+    if (D.n <= kLdsJobs) {
+        for (int i = threadIdx.x; i < D.n; i += blockDim.x) {
+            s_begin[i] = A.dir_begin ? A.dir_begin[i] : A.jobs[i].ray_begin;
+            s_job[i] = A.dir_begin ? A.dir_job[i] : i;
+        }
+        __syncthreads();
+        D.begin = s_begin;
+        D.job = s_job;
+    }
     Ray R;
     bool active = false;
     bool parked = false;       // this lane used its step budget for this launch
     bool exhausted = false;
+    int done = -1;             // serving: job of a ray that ended this iteration
     long long budget = A.step_budget;
     const long long slot = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (A.slots && A.slot_live[slot]) {
         unpark(R, A.slots + slot * SLOT_DOUBLES);
         A.slot_live[slot] = 0u;
-        active = !drop_if_cancelled(R, A);
+        active = !A.jobs[R.job].cancelled;
+        if (!active) done = R.job;
     }
+    if (A.remaining) count_done(A, done);
     // this wavefront's current chunk of ray ids [next, end) (wave-uniform values)
     long long next = 0, end = 0;
     const long long n_rays = A.total_rays - A.first_ray;
@@ -710,9 +761,10 @@ trace_persistent(LaunchArgs A)
                 }
                 if (id >= 0) {
                     if (A.order) id = (long long)A.order[id];
-                    ray_init<KIND>(R, A.first_ray + id, A, M);
-                    active = !drop_if_cancelled(R, A);
+                    active = ray_init<KIND>(R, A.first_ray + id, A, D, M);
+                    if (!active) done = R.job;
                 }
+                if (A.remaining) count_done(A, done);
             }
         }
         if (!__any(active)) {
@@ -721,13 +773,16 @@ trace_persistent(LaunchArgs A)
         }
         if (active) {
             active = !ray_step<KIND, PREC>(R, A, M);
-            if (active && A.slots && --budget == 0) {
+            if (!active) {
+                done = R.job;
+            } else if (A.slots && --budget == 0) {
                 park(R, A.slots + slot * SLOT_DOUBLES);
                 A.slot_live[slot] = 1u;
                 active = false;
                 parked = true;
             }
         }
+        if (A.remaining) count_done(A, done);
     }
 }
 

@@ -7,6 +7,7 @@ the library is loaded so that both use the same HIP runtime.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -92,6 +93,8 @@ def lib():
         L.tartarus_last_error.restype = C.c_char_p
         L.tartarus_last_error.argtypes = []
         _lib = L
+        # the serving thread must be stopped while the HIP runtime is still up
+        atexit.register(L.tartarus_shutdown)
     return _lib
 
 
