@@ -129,12 +129,25 @@ def cpu_baseline(w, solver, seconds: float) -> dict:
                       f"plain FP64 C oracle, OpenMP over pixels, {dt:.1f} s"}
 
 
-def serving_leg(T, torch, W, value_rtol8: float, n_requests: int, load: float = 0.8, seed: int = 0) -> dict:
+def serving_leg(T, torch, W, n_requests: int, load: float = 0.8, seed: int = 0) -> dict:
     """Poisson stream of image requests (resolution uniform over 64^2..1024^2,
     spin, inclination, disk size drawn per request) submitted at their arrival
-    times through tartarus_submit; latency = done - submit per request."""
+    times through tartarus_submit; latency = done - submit per request.  The
+    offered load is a fraction of the server's own throughput, measured first
+    on a burst of requests from the same distribution (another seed)."""
+    mk = lambda r: (T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
+                    T.make_solver(r["solver"]))
+    # capacity: a burst submitted at once
+    burst = W.request_stream(seed + 1000, 48, 1e9)
+    bouts = [T.alloc_outputs(r["camera"]["nx"] * r["camera"]["ny"]) for r in burst]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in [T.tartarus_submit(*mk(r), o) for r, o in zip(burst, bouts)]:
+        T.tartarus_wait(t, 120000)
+    capacity = sum(r["camera"]["nx"] * r["camera"]["ny"] for r in burst) / (time.perf_counter() - t0)
+    del bouts
     mean_rays = float(np.mean([r * r for r in W.RESOLUTIONS]))
-    rate = load * value_rtol8 / mean_rays
+    rate = load * capacity / mean_rays
     reqs = W.request_stream(seed, n_requests, rate)
     outs = [T.alloc_outputs(r["camera"]["nx"] * r["camera"]["ny"]) for r in reqs]
     torch.cuda.synchronize()
@@ -144,8 +157,7 @@ def serving_leg(T, torch, W, value_rtol8: float, n_requests: int, load: float = 
         delay = r["arrival_s"] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        tickets.append(T.tartarus_submit(T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
-                                         T.make_solver(r["solver"]), o))
+        tickets.append(T.tartarus_submit(*mk(r), o))
     for t in tickets:
         T.tartarus_wait(t, 120000)
     stamps = np.array([T.tartarus_ticket_times(t) for t in tickets], dtype=np.float64)
@@ -156,11 +168,13 @@ def serving_leg(T, torch, W, value_rtol8: float, n_requests: int, load: float = 
     failed = int(sum(int((T.to_numpy({"cls": o["cls"]})["cls"] == 2).sum()) for o in outs))
     T.tartarus_shutdown()
     T.tartarus_init(0, 0)
-    return {"requests": len(reqs), "load": load, "arrival_rate_per_s": rate, "precision": "fp64",
-            "rtol": reqs[0]["solver"]["rtol"], "p50_latency_ms": float(np.percentile(lat_ms[warm:], 50)),
+    return {"requests": len(reqs), "load": load, "capacity_rays_per_s": capacity, "arrival_rate_per_s": rate,
+            "precision": "fp64", "rtol": reqs[0]["solver"]["rtol"],
+            "p50_latency_ms": float(np.percentile(lat_ms[warm:], 50)),
             "p99_latency_ms": float(np.percentile(lat_ms[warm:], 99)),
             "max_latency_ms": float(lat_ms[warm:].max()), "rays_per_s": rays / span, "failed_rays": failed,
-            "note": "latency = completion - submission; first 10 requests are warm-up"}
+            "note": "latency = completion - submission; first 10 requests are warm-up; "
+                    "load = fraction of the burst capacity"}
 
 
 def main():
@@ -273,8 +287,7 @@ def main():
 
     if not args.no_serving:
         log("bench: serving leg")
-        result["serving"] = serving_leg(T, torch, W, value_rtol8=result.get("legs", {}).get(
-            "fp64_rtol1e-8", {}).get("rays_per_s", value), n_requests=args.serving_requests)
+        result["serving"] = serving_leg(T, torch, W, n_requests=args.serving_requests)
     if tuned:
         result["launch_shape"] = {k: dict(zip(SHAPE_KEYS, v)) for k, v in tuned.items()}
     if not args.no_cpu:

@@ -112,6 +112,38 @@ def test_kerr_ragged_with_disk(T, orc):
     assert (o["n_hits"] > 0).sum() > 50
 
 
+def test_narrow_disk_ring_edges(T, orc):
+    """A ring r in [3, 4]: many equatorial crossings straddle an edge of the disk
+    within one step, so the integrator locates those roots itself while the rest
+    are left to the finishing pass; both must agree with the oracle."""
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=48, ny=40, alpha_min=-9.0, alpha_max=9.0, beta_min=-8.0, beta_max=8.0)
+    for max_hits in (3, 1):
+        disk = dict(w["disk"], r_in=3.0, r_out=4.0, max_hits=max_hits)
+        say("case ring 3..4, max_hits", max_hits)
+        g, o = full_image_parity(T, orc, w["a"], cam, disk, w["solver"])
+        assert (o["n_hits"] > 0).sum() > 100
+        assert np.array_equal(g["hit_order"], o["hit_order"]) or np.mean(g["hit_order"] == o["hit_order"]) > 0.99
+
+
+def test_more_cameras_than_the_lds_directory(T, orc):
+    """1100 cameras in one launch (the job directory no longer fits in LDS):
+    identical to the same cameras traced in launches of 550; a few cameras are
+    checked against the oracle."""
+    w = W.WORKLOADS["kerr09_512"]
+    base = w["cameras"][0]
+    cams = [dict(base, nx=3, ny=3, theta_obs=(5.0 + 80.0 * k / 1099) * math.pi / 180.0) for k in range(1100)]
+    say("case 1100 cameras")
+    g = gpu_trace(T, w["a"], cams, w["disk"], w["solver"])
+    parts = [gpu_trace(T, w["a"], cams[i:i + 550], w["disk"], w["solver"]) for i in (0, 550)]
+    for k in g:
+        assert np.array_equal(g[k], np.concatenate([p[k] for p in parts])), k
+    for c in (0, 549, 1099):
+        o = oracle_trace(orc, w["a"], cams[c], w["disk"], w["solver"])
+        gs = {k: v[9 * c:9 * c + 9] for k, v in g.items()}
+        assert np.array_equal(gs["cls"], o["cls"]) and np.array_equal(gs["n_hits"], o["n_hits"])
+
+
 def test_single_pixel_and_single_row(T, orc):
     w = W.WORKLOADS["kerr09_512"]
     for nx, ny in ((1, 1), (17, 1), (1, 5)):
