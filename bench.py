@@ -129,6 +129,40 @@ def cpu_baseline(w, solver, seconds: float) -> dict:
                       f"plain FP64 C oracle, OpenMP over pixels, {dt:.1f} s"}
 
 
+def workload_legs(T, torch, W, out_cache, steps: int = 2) -> dict:
+    """rays/s of the other image workloads (default launch, rtol 1e-8): the
+    Schwarzschild shadow, the a = 0.998 2048^2 scene in FP64 and mixed, the
+    paper's OSIRIS calibration scene, and the 64-camera tabulated-metric batch."""
+    legs = {}
+    for name, prec in (("schwarzschild_64", T.PREC_FP64), ("kerr0998_2048", T.PREC_FP64),
+                       ("kerr0998_2048", T.PREC_MIXED), ("osiris_1024", T.PREC_FP64),
+                       ("tabulated07_64cams", T.PREC_FP64)):
+        w = W.WORKLOADS[name]
+        cams = [T.make_camera(c) for c in w["cameras"]]
+        n = sum(c["nx"] * c["ny"] for c in w["cameras"])
+        if "table" in w:
+            t = w["table"]
+            r_min = t["r_min_over_rplus"] * (1.0 + np.sqrt(1.0 - w["a"] ** 2))
+            tab = torch.zeros(5 * t["nr"] * t["nth"] * 4, dtype=torch.float64, device="cuda")
+            T.tartarus_build_kerr_table(w["a"], t["nr"], t["nth"], r_min, t["r_max"], tab)
+            metric = T.make_metric(w["a"], tab, t["nr"], t["nth"], r_min, t["r_max"])
+        else:
+            metric = T.make_metric(w["a"])
+        if n not in out_cache:
+            out_cache.clear()
+            out_cache[n] = T.alloc_outputs(n)
+        out = out_cache[n]
+        la = (metric, cams, T.make_disk(w["disk"]), T.make_solver(w["solver"], prec))
+        log("bench: workload", name, "mixed" if prec else "fp64")
+        wl, km = time_leg(T, torch, la, out, steps, 1)
+        o = T.to_numpy(out)
+        att = o["n_accept"] + o["n_reject"]
+        legs[f"{name}_{'mixed' if prec else 'fp64'}"] = {
+            "rays": n, "rays_per_s": n * steps / wl, "kernel_ms": km, "attempts_per_ray": float(att.mean()),
+            "failed_rays": int((o["cls"] == 2).sum())}
+    return legs
+
+
 def serving_leg(T, torch, W, n_requests: int, load: float = 0.8, seed: int = 0) -> dict:
     """Poisson stream of image requests (resolution uniform over 64^2..1024^2,
     spin, inclination, disk size drawn per request) submitted at their arrival
@@ -281,6 +315,7 @@ def main():
                           "fp32_attempt_frac": float(ol["n_fp32"].sum() / attl.sum()),
                           "gate_frac_le_1e-8": float(np.mean(ol["h_gate"] <= 1e-8)),
                           "failed_rays": int((ol["cls"] == 2).sum())}
+        legs.update(workload_legs(T, torch, W, {}))
         legs["mixed_over_fp64_same_rtol"] = legs["mixed_rtol1e-8"]["rays_per_s"] / legs["fp64_rtol1e-8"]["rays_per_s"]
         legs["mixed_rtol1e-8_over_fp64_gate"] = legs["mixed_rtol1e-8"]["rays_per_s"] / value
         result["legs"] = legs

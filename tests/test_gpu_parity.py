@@ -121,9 +121,24 @@ def test_narrow_disk_ring_edges(T, orc):
     for max_hits in (3, 1):
         disk = dict(w["disk"], r_in=3.0, r_out=4.0, max_hits=max_hits)
         say("case ring 3..4, max_hits", max_hits)
-        g, o = full_image_parity(T, orc, w["a"], cam, disk, w["solver"])
+        g = gpu_trace(T, w["a"], cam, disk, w["solver"])
+        o = oracle_trace(orc, w["a"], cam, disk, w["solver"])
+        # a ring image has hit-count edges everywhere, so compare every ray whose
+        # class and hit count agree (a disagreement needs a crossing within
+        # rounding of r_in or r_out)
+        same = (g["cls"] == o["cls"]) & (g["n_hits"] == o["n_hits"])
+        say("rays", same.size, "class/hit-count disagreements", int((~same).sum()))
+        assert (~same).sum() <= 2
         assert (o["n_hits"] > 0).sum() > 100
-        assert np.array_equal(g["hit_order"], o["hit_order"]) or np.mean(g["hit_order"] == o["hit_order"]) > 0.99
+        for k in range(max_hits):
+            m = same & (o["n_hits"] > k)
+            if not m.any():
+                continue
+            er = np.abs(g["hit_r"][m, k] / o["hit_r"][m, k] - 1).max()
+            eg = np.abs(g["hit_g"][m, k] / o["hit_g"][m, k] - 1).max()
+            say("slot", k, "hits", int(m.sum()), "max rel err r", er, "g", eg)
+            assert er <= FP64_TOL and eg <= FP64_TOL
+            assert np.array_equal(g["hit_order"][m, k], o["hit_order"][m, k])
 
 
 def test_more_cameras_than_the_lds_directory(T, orc):
