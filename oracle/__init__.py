@@ -47,7 +47,7 @@ class Disk(C.Structure):
 class Solver(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0_frac", C.c_double),
                 ("horizon_factor", C.c_double), ("r_escape", C.c_double), ("event_tol", C.c_double),
-                ("max_steps", C.c_int64)]
+                ("max_steps", C.c_int64), ("method", C.c_int32), ("pad", C.c_int32)]
 
 
 class Outputs(C.Structure):
@@ -86,6 +86,8 @@ def lib():
         L.or_redshift.restype = C.c_double
         L.or_dp45_tableau.argtypes = [dp, dp, dp, dp]
         L.or_dp45_fixed.argtypes = [C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
+        L.or_rk_tableau.argtypes = [C.c_int, dp, dp, dp, dp]
+        L.or_rk_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
         L.or_hermite.argtypes = [C.c_double] * 6
         L.or_hermite.restype = C.c_double
         L.or_bisect_count.argtypes = [C.c_double, C.c_double]
@@ -129,7 +131,7 @@ def make_disk(d: dict | None) -> Disk:
 
 def make_solver(s: dict) -> Solver:
     return Solver(s["rtol"], s["atol"], s.get("h0_frac", 0.01), s.get("horizon_factor", 1.01),
-                  s["r_escape"], s.get("event_tol", 1e-12), s.get("max_steps", 1_000_000))
+                  s["r_escape"], s.get("event_tol", 1e-12), s.get("max_steps", 1_000_000), s.get("method", 0), 0)
 
 
 def alloc_outputs(n: int) -> dict:
@@ -210,14 +212,27 @@ def bisect_count(h, tol): return lib().or_bisect_count(h, tol)
 def max_threads(): return lib().or_max_threads()
 
 
+METHODS = {"dp45": 0, "ck45": 1, "rkf45": 2}
+
+
 def dp45_tableau():
+    return rk_tableau(0)
+
+
+def rk_tableau(method: int):
+    """(c, a[7][6], b, b*) of a 5(4) pair: 0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg."""
     c, a, b, bs = np.zeros(7), np.zeros(42), np.zeros(7), np.zeros(7)
-    lib().or_dp45_tableau(_dptr(c), _dptr(a), _dptr(b), _dptr(bs))
+    lib().or_rk_tableau(method, _dptr(c), _dptr(a), _dptr(b), _dptr(bs))
     return c, a.reshape(7, 6), b, bs
 
 
 def dp45_fixed(f, y0, h: float, nsteps: int):
-    """Fixed-step DP45 on y' = f(y) (f: numpy array -> numpy array); returns (y, last error vector)."""
+    return rk_fixed(0, f, y0, h, nsteps)
+
+
+def rk_fixed(method: int, f, y0, h: float, nsteps: int):
+    """Fixed-step steps of a 5(4) pair on y' = f(y) (f: numpy array -> numpy array); returns
+    (y, last error vector)."""
     n = len(y0)
 
     def cb(yp, dyp, nn):
@@ -229,7 +244,7 @@ def dp45_fixed(f, y0, h: float, nsteps: int):
     cfun = USER_RHS(cb)
     y = np.ascontiguousarray(y0, dtype=np.float64).copy()
     e = np.zeros(n)
-    lib().or_dp45_fixed(n, cfun, _dptr(y), h, nsteps, _dptr(e))
+    lib().or_rk_fixed(method, n, cfun, _dptr(y), h, nsteps, _dptr(e))
     return y, e
 
 

@@ -372,66 +372,101 @@ void or_initial_state(const or_metric* m, const or_camera* cam, int i, int j, do
 }
 
 /* ------------------------------------------------------------------ */
-/* Dormand-Prince 5(4) (Sec. 3.2; Dormand & Prince 1980 coefficients).  */
+/* Embedded Runge-Kutta 5(4) pairs (Sec. 3.2): Dormand & Prince (1980),  */
+/* Cash & Karp (1990), Fehlberg (1969).  The fifth-order weights         */
+/* propagate the solution, the embedded fourth-order weights give the    */
+/* error estimate.  Each pair is stored as seven stages: the six of the  */
+/* method and a seventh evaluation f(y5) at the new point (the first     */
+/* stage of Dormand-Prince's next step; for the two six-stage pairs the  */
+/* derivative the next step starts from and the event interpolant uses). */
+/* Row 6 of A is therefore b, and only Dormand-Prince's embedded weights */
+/* give the seventh evaluation a nonzero weight.                         */
 /* ------------------------------------------------------------------ */
-static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
-static const double DP_A[7][6] = {
-    {0, 0, 0, 0, 0, 0},
-    {1.0 / 5.0, 0, 0, 0, 0, 0},
-    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
-    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},
-    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0},
-    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0},
-    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}};
+static const double RK_C[3][7] = {
+    {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0},
+    {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0, 1.0},
+    {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0, 1.0}};
+static const double RK_A[3][7][6] = {
+    {{0, 0, 0, 0, 0, 0},
+     {1.0 / 5.0, 0, 0, 0, 0, 0},
+     {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+     {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},
+     {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0},
+     {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0},
+     {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}},
+    {{0, 0, 0, 0, 0, 0},
+     {1.0 / 5.0, 0, 0, 0, 0, 0},
+     {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+     {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0, 0},
+     {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0, 0},
+     {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0, 0},
+     {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0}},
+    {{0, 0, 0, 0, 0, 0},
+     {1.0 / 4.0, 0, 0, 0, 0, 0},
+     {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0, 0},
+     {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0, 0},
+     {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0, 0},
+     {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0, 0},
+     {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0}}};
 /* fifth-order weights (propagate: local extrapolation) */
-static const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+static const double RK_B[3][7] = {
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0.0},
+    {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0, 0.0},
+    {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0, 0.0}};
 /* embedded fourth-order weights (error estimate) */
-static const double DP_BS[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
-                                -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+static const double RK_BS[3][7] = {
+    {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0},
+    {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0, 1.0 / 4.0, 0.0},
+    {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0, 0.0}};
 
-void or_dp45_tableau(double* c, double* a, double* b, double* bstar)
+void or_rk_tableau(int method, double* c, double* a, double* b, double* bstar)
 {
     for (int i = 0; i < 7; ++i) {
-        c[i] = DP_C[i];
-        b[i] = DP_B[i];
-        bstar[i] = DP_BS[i];
-        for (int j = 0; j < 6; ++j) a[i * 6 + j] = DP_A[i][j];
+        c[i] = RK_C[method][i];
+        b[i] = RK_B[method][i];
+        bstar[i] = RK_BS[method][i];
+        for (int j = 0; j < 6; ++j) a[i * 6 + j] = RK_A[method][i][j];
     }
 }
+
+void or_dp45_tableau(double* c, double* a, double* b, double* bstar) { or_rk_tableau(0, c, a, b, bstar); }
 
 typedef void (*rhs_fn)(void* ctx, const double* y, double* dy);
 
 /* One attempted step of size h from y with k1 = f(y): writes the fifth-order
  * solution y5, the error vector err = h * sum (b - b*) k, and k7 = f(y5). */
-static void dp45_attempt(int n, rhs_fn f, void* ctx, const double* y, const double* k1, double h,
-                         double* y5, double* err, double* k7)
+static void rk_attempt(int method, int n, rhs_fn f, void* ctx, const double* y, const double* k1, double h,
+                       double* y5, double* err, double* k7)
 {
+    const double(*A)[6] = RK_A[method];
+    const double* B = RK_B[method];
+    const double* BS = RK_BS[method];
     double k[7][NSTATE > 16 ? NSTATE : 16];
     double Y[16];
     for (int d = 0; d < n; ++d) k[0][d] = k1[d];
     for (int s = 1; s < 6; ++s) {
         for (int d = 0; d < n; ++d) {
             double acc = 0.0;
-            for (int j = 0; j < s; ++j) acc += DP_A[s][j] * k[j][d];
+            for (int j = 0; j < s; ++j) acc += A[s][j] * k[j][d];
             Y[d] = y[d] + h * acc;
         }
         f(ctx, Y, k[s]);
     }
     for (int d = 0; d < n; ++d) {
         double acc = 0.0;
-        for (int j = 0; j < 6; ++j) acc += DP_B[j] * k[j][d];
+        for (int j = 0; j < 6; ++j) acc += B[j] * k[j][d];
         y5[d] = y[d] + h * acc;
     }
     f(ctx, y5, k[6]);
     for (int d = 0; d < n; ++d) {
         double acc = 0.0;
-        for (int j = 0; j < 7; ++j) acc += (DP_B[j] - DP_BS[j]) * k[j][d];
+        for (int j = 0; j < 7; ++j) acc += (B[j] - BS[j]) * k[j][d];
         err[d] = h * acc;
         k7[d] = k[6][d];
     }
 }
 
-/* Test hook: fixed-step DP45 on a user ODE (y' = f(y), n <= 16). */
+/* Test hook: fixed-step steps of a 5(4) pair on a user ODE (y' = f(y), n <= 16). */
 typedef void (*or_user_rhs)(const double* y, double* dy, int n);
 struct user_ctx { or_user_rhs f; int n; };
 static void user_tramp(void* ctx, const double* y, double* dy)
@@ -439,15 +474,20 @@ static void user_tramp(void* ctx, const double* y, double* dy)
     struct user_ctx* u = (struct user_ctx*)ctx;
     u->f(y, dy, u->n);
 }
-void or_dp45_fixed(int n, or_user_rhs f, double* y, double h, int nsteps, double* last_err)
+void or_rk_fixed(int method, int n, or_user_rhs f, double* y, double h, int nsteps, double* last_err)
 {
     struct user_ctx u = {f, n};
     double k1[16], y5[16], e[16], k7[16];
     f(y, k1, n);
     for (int s = 0; s < nsteps; ++s) {
-        dp45_attempt(n, user_tramp, &u, y, k1, h, y5, e, k7);
+        rk_attempt(method, n, user_tramp, &u, y, k1, h, y5, e, k7);
         for (int d = 0; d < n; ++d) { y[d] = y5[d]; k1[d] = k7[d]; last_err[d] = e[d]; }
     }
+}
+
+void or_dp45_fixed(int n, or_user_rhs f, double* y, double h, int nsteps, double* last_err)
+{
+    or_rk_fixed(0, n, f, y, h, nsteps, last_err);
 }
 
 /* ------------------------------------------------------------------ */
@@ -567,7 +607,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
 
     for (;;) {
         if ((int64_t)out->n_accept + out->n_reject >= sv->max_steps) break;
-        dp45_attempt(NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
+        rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
         /* RMS error norm over all eight components */
         double acc = 0.0;
         for (int d = 0; d < NSTATE; ++d) {

@@ -38,9 +38,12 @@ typedef struct {
     int max_hits;          /* 0..3; 0 = no disk                                      */
 } or_disk;
 
+/* method: 0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg 5(4) pair (Sec. 3.2). */
 typedef struct {
     double rtol, atol, h0_frac, horizon_factor, r_escape, event_tol;
     int64_t max_steps;
+    int32_t method;
+    int32_t pad;
 } or_solver;
 
 /* Structure-of-arrays outputs, indexed by position in the traced ray list. */

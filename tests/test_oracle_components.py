@@ -140,8 +140,12 @@ def order_conditions(b, A, c):
     return conds
 
 
-def test_dp45_tableau_order_conditions(orc):
-    c, a6, b, bs = orc.dp45_tableau()
+@pytest.mark.parametrize("method", [0, 1, 2], ids=["dp45", "ck45", "rkf45"])
+def test_rk_tableau_order_conditions(orc, method):
+    """Each 5(4) pair of Sec. 3.2 (Dormand-Prince, Cash-Karp, Fehlberg): the
+    propagating weights satisfy all 17 order conditions up to order 5, the
+    embedded ones those up to order 4 and not all of order 5."""
+    c, a6, b, bs = orc.rk_tableau(method)
     A = np.zeros((7, 7), dtype=object)
     A[:, :] = Fraction(0)
     A[:, :6] = as_fractions(a6)
@@ -158,12 +162,13 @@ def test_dp45_tableau_order_conditions(orc):
     assert any(v != want for v, want in emb[8:])  # ... and not fifth
 
 
-def test_dp45_convergence_order_five(orc):
+@pytest.mark.parametrize("method", [0, 1, 2], ids=["dp45", "ck45", "rkf45"])
+def test_rk_convergence_order_five(orc, method):
     f = lambda y: np.array([y[1], -y[0]])
     T = 2.0
     errs, ests = [], []
     for N in (10, 20, 40):
-        y, e = orc.dp45_fixed(f, [1.0, 0.0], T / N, N)
+        y, e = orc.rk_fixed(method, f, [1.0, 0.0], T / N, N)
         errs.append(np.hypot(y[0] - math.cos(T), y[1] + math.sin(T)))
         ests.append(np.abs(e).max())
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]

@@ -68,11 +68,13 @@ def edge_band(cls2d):
     return band
 
 
-@pytest.mark.parametrize("a,th_deg,nx,w", [(0.0, 90.0, 64, 10.0), (0.9, 60.0, 40, 12.0), (0.998, 17.0, 40, 10.0)])
-def test_capture_matches_exact_criterion(orc, a, th_deg, nx, w):
+@pytest.mark.parametrize("a,th_deg,nx,w,method", [(0.0, 90.0, 64, 10.0, 0), (0.9, 60.0, 40, 12.0, 0),
+                                                   (0.998, 17.0, 40, 10.0, 0), (0.9, 60.0, 24, 12.0, 1),
+                                                   (0.9, 60.0, 24, 12.0, 2)])
+def test_capture_matches_exact_criterion(orc, a, th_deg, nx, w, method):
     c = W.camera(D, th_deg, nx, nx, w)
     m = orc.make_metric(a)
-    o = orc.trace(m, orc.make_camera(c), orc.make_disk(None), orc.make_solver(W.solver()))
+    o = orc.trace(m, orc.make_camera(c), orc.make_disk(None), orc.make_solver(W.solver(method=method)))
     cls = o["cls"].reshape(nx, nx)
     assert not np.any(cls == orc.FAILED)
     rp = orc.horizon(a)
@@ -149,9 +151,11 @@ def test_bardeen_curve_extents():
         assert be.max() == pytest.approx(bmax, abs=2e-3)
 
 
+@pytest.mark.parametrize("method", [0, 1, 2], ids=["dp45", "ck45", "rkf45"])
 @pytest.mark.parametrize("alpha", [6.5, 9.0, 15.0])
-def test_schwarzschild_deflection_quadrature(orc, alpha):
-    """Equatorial escape: total phi swept between r = 1000 (start) and r = 1100 (stop)."""
+def test_schwarzschild_deflection_quadrature(orc, alpha, method):
+    """Equatorial escape: total phi swept between r = 1000 (start) and r = 1100 (stop),
+    with each 5(4) pair of Sec. 3.2."""
     b = alpha / math.sqrt(1 - 2 / D)
     P = lambda u: 1 / b ** 2 - u * u + 2 * u ** 3
     roots = np.roots([2.0, -1.0, 0.0, 1 / b ** 2])
@@ -163,7 +167,7 @@ def test_schwarzschild_deflection_quadrature(orc, alpha):
                     epsabs=1e-13, epsrel=1e-13, limit=400)[0]
 
     expect = leg(1 / D) + leg(1 / 1100.0)
-    o = single_ray(orc, 0.0, 90.0, alpha, 0.0, solver=W.solver(rtol=1e-12, atol=1e-14))
+    o = single_ray(orc, 0.0, 90.0, alpha, 0.0, solver=W.solver(rtol=1e-12, atol=1e-14, method=method))
     assert o["cls"][0] == orc.ESCAPED
     assert abs(o["final_rtp"][0, 2]) == pytest.approx(expect, rel=2e-9)
     assert o["final_rtp"][0, 0] == pytest.approx(1100.0, abs=1e-9)
