@@ -315,6 +315,16 @@ def main():
                           "fp32_attempt_frac": float(ol["n_fp32"].sum() / attl.sum()),
                           "gate_frac_le_1e-8": float(np.mean(ol["h_gate"] <= 1e-8)),
                           "failed_rays": int((ol["cls"] == 2).sum())}
+        # the other two 5(4) pairs of Sec. 3.2 on the same image, rtol 1e-8
+        for mname, mcode in (("ck45", T.METHOD_CK45), ("rkf45", T.METHOD_RKF45)):
+            la = (metric, cams, disk, T.make_solver(dict(w["solver"], method=mcode), T.PREC_FP64))
+            log("bench: leg", mname)
+            wl, km = time_leg(T, torch, la, out, args.steps, args.warmup)
+            ol = T.to_numpy(out)
+            attl = ol["n_accept"] + ol["n_reject"]
+            legs[f"{mname}_rtol1e-8"] = {"rays_per_s": n * args.steps / wl, "kernel_ms": km,
+                                         "attempts_per_ray": float(attl.mean()),
+                                         "failed_rays": int((ol["cls"] == 2).sum())}
         legs.update(workload_legs(T, torch, W, {}))
         legs["mixed_over_fp64_same_rtol"] = legs["mixed_rtol1e-8"]["rays_per_s"] / legs["fp64_rtol1e-8"]["rays_per_s"]
         legs["mixed_rtol1e-8_over_fp64_gate"] = legs["mixed_rtol1e-8"]["rays_per_s"] / value

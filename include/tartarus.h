@@ -114,7 +114,12 @@ typedef struct {
  * (attempted steps, accepted + rejected).  precision: TARTARUS_PREC_FP64, or
  * TARTARUS_PREC_MIXED (Runge-Kutta stages evaluated in FP32 in the far field;
  * state sums, error norm, controller, events and shading stay FP64).
- * method: 0 = Dormand-Prince 5(4) (the only one provided). */
+ * method: the embedded 5(4) pair, TARTARUS_METHOD_DP45 (Dormand-Prince),
+ * TARTARUS_METHOD_CK45 (Cash-Karp) or TARTARUS_METHOD_RKF45 (Fehlberg); each
+ * propagates the fifth-order solution and controls the step with the embedded
+ * fourth-order estimate (Sec. 3.2).  Mixed precision and the tabulated metric
+ * need DP45. */
+enum { TARTARUS_METHOD_DP45 = 0, TARTARUS_METHOD_CK45 = 1, TARTARUS_METHOD_RKF45 = 2 };
 typedef struct {
     double rtol, atol, h0_frac, horizon_factor, r_escape, event_tol;
     int64_t max_steps;

@@ -27,12 +27,12 @@
 
 using namespace tartarus;
 
-extern "C" hipError_t tartarus_launch_trace(int kind, int prec, const LaunchArgs* args, int grid, int block,
+extern "C" hipError_t tartarus_launch_trace(int kind, int prec, int method, const LaunchArgs* args, int grid, int block,
                                             hipStream_t stream);
 extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_finish(const LaunchArgs* args, int job0, int njobs, long long max_rays,
                                             hipStream_t stream);
-extern "C" hipError_t tartarus_occupancy(int kind, int prec, int block, int* blocks_per_cu);
+extern "C" hipError_t tartarus_occupancy(int kind, int prec, int method, int block, int* blocks_per_cu);
 extern "C" hipError_t tartarus_launch_build_table(double a, int nr, int nth, double r_min, double r_max,
                                                   double* table, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_order(const LaunchArgs* args, long long total, unsigned char* key,
@@ -97,7 +97,7 @@ struct Device {
     std::mutex mu;                       // guards the slots and the tuning table
     Slot slots[kSlots];
     int next_slot = 0;
-    std::map<int, tartarus_launch> tuned;  // key: kind * 2 + precision
+    std::map<int, tartarus_launch> tuned;  // key: tune_key(kind, precision, method)
 };
 Device g_dev;
 
@@ -132,7 +132,7 @@ int take_slot(int njobs, Slot*& out)
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int check_metric(const tartarus_metric* m, int precision)
+int check_metric(const tartarus_metric* m, int precision, int method)
 {
     if (!m) return fail(TARTARUS_E_INVALID, "metric is NULL");
     if (!(std::isfinite(m->a) && m->a >= 0.0 && m->a < 1.0)) return fail(TARTARUS_E_INVALID, "spin a must be in [0, 1)");
@@ -143,6 +143,8 @@ int check_metric(const tartarus_metric* m, int precision)
             return fail(TARTARUS_E_INVALID, "table needs 0 < r_min < r_max");
         if (precision != TARTARUS_PREC_FP64)
             return fail(TARTARUS_E_INVALID, "the tabulated metric is traced in FP64 only");
+        if (method != TARTARUS_METHOD_DP45)
+            return fail(TARTARUS_E_INVALID, "the tabulated metric is traced with Dormand-Prince 5(4) only");
     } else if (m->kind != TARTARUS_METRIC_KERR) {
         return fail(TARTARUS_E_INVALID, "unknown metric kind");
     }
@@ -180,7 +182,10 @@ int check_solver(const tartarus_solver* s)
     if (s->max_steps < 1) return fail(TARTARUS_E_INVALID, "max_steps must be >= 1");
     if (s->precision != TARTARUS_PREC_FP64 && s->precision != TARTARUS_PREC_MIXED)
         return fail(TARTARUS_E_INVALID, "unknown precision");
-    if (s->method != 0) return fail(TARTARUS_E_INVALID, "only method 0 (Dormand-Prince 5(4)) is provided");
+    if (s->method < TARTARUS_METHOD_DP45 || s->method > TARTARUS_METHOD_RKF45)
+        return fail(TARTARUS_E_INVALID, "unknown method (0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg)");
+    if (s->precision == TARTARUS_PREC_MIXED && s->method != TARTARUS_METHOD_DP45)
+        return fail(TARTARUS_E_INVALID, "mixed precision is provided with Dormand-Prince 5(4) only");
     return TARTARUS_OK;
 }
 
@@ -211,7 +216,7 @@ int validate_all(const tartarus_metric* metric, const tartarus_camera* cams, int
 {
     int rc;
     if ((rc = check_solver(solver))) return rc;
-    if ((rc = check_metric(metric, solver->precision))) return rc;
+    if ((rc = check_metric(metric, solver->precision, solver->method))) return rc;
     if ((rc = check_disk(disk))) return rc;
     if (!cams || ncams < 1) return fail(TARTARUS_E_INVALID, "need at least one camera");
     for (int c = 0; c < ncams; ++c) {
@@ -289,9 +294,11 @@ void fill_args(LaunchArgs& A, const tartarus_metric* m, const tartarus_solver* s
     }
 }
 
-tartarus_launch default_launch(int kind, int prec)
+int tune_key(int kind, int prec, int method) { return (kind * 2 + prec) * 3 + method; }
+
+tartarus_launch default_launch(int kind, int prec, int method)
 {
-    auto it = g_dev.tuned.find(kind * 2 + prec);
+    auto it = g_dev.tuned.find(tune_key(kind, prec, method));
     if (it != g_dev.tuned.end()) return it->second;
     tartarus_launch L;
     L.block_threads = 256;
@@ -302,9 +309,9 @@ tartarus_launch default_launch(int kind, int prec)
     return L;
 }
 
-int resolve_launch(int kind, int prec, const tartarus_launch* req, tartarus_launch& L, int& grid)
+int resolve_launch(int kind, int prec, int method, const tartarus_launch* req, tartarus_launch& L, int& grid)
 {
-    L = default_launch(kind, prec);
+    L = default_launch(kind, prec, method);
     if (req) {
         if (req->block_threads > 0) L.block_threads = req->block_threads;
         if (req->blocks_per_cu > 0) L.blocks_per_cu = req->blocks_per_cu;
@@ -318,7 +325,7 @@ int resolve_launch(int kind, int prec, const tartarus_launch* req, tartarus_laun
     if (L.refill_min < 1 || L.refill_min > 64) return fail(TARTARUS_E_INVALID, "refill_min must be in 1..64");
     if (L.chunk < 1) return fail(TARTARUS_E_INVALID, "chunk must be >= 1");
     int occ = 0;
-    HIP_TRY(tartarus_occupancy(kind, prec, L.block_threads, &occ));
+    HIP_TRY(tartarus_occupancy(kind, prec, method, L.block_threads, &occ));
     if (occ < 1) return fail(TARTARUS_E_DEVICE, "kernel cannot be resident with this block size");
     if (L.blocks_per_cu <= 0 || L.blocks_per_cu > occ) L.blocks_per_cu = occ;
     grid = g_dev.cus * L.blocks_per_cu;
@@ -330,10 +337,10 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
                   const tartarus_solver* solver, const tartarus_outputs* out, const tartarus_launch* launch,
                   hipStream_t stream)
 {
-    const int kind = metric->kind, prec = solver->precision;
+    const int kind = metric->kind, prec = solver->precision, method = solver->method;
     tartarus_launch L;
     int grid = 0;
-    int rc = resolve_launch(kind, prec, launch, L, grid);
+    int rc = resolve_launch(kind, prec, method, launch, L, grid);
     if (rc) return rc;
     Slot* S = nullptr;
     if ((rc = take_slot(ncams, S))) return rc;
@@ -382,7 +389,7 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
         HIP_TRY(tartarus_launch_order(&A, n, key, count, cursor, order, stream));
         A.order = order;
     }
-    HIP_TRY(tartarus_launch_trace(kind, prec, &A, grid, L.block_threads, stream));
+    HIP_TRY(tartarus_launch_trace(kind, prec, method, &A, grid, L.block_threads, stream));
     for (int c0 = 0; c0 < ncams; c0 += 65535)
         HIP_TRY(tartarus_launch_finish(&A, c0, std::min(65535, ncams - c0), per, stream));
     HIP_TRY(hipEventRecord(S->ev, stream));
@@ -501,11 +508,11 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
     if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
     HIP_TRY(hipSetDevice(g_dev.id));
     hipStream_t stream = (hipStream_t)hip_stream;
-    const int kind = metric->kind, prec = solver->precision;
-    g_dev.tuned.erase(kind * 2 + prec);
-    tartarus_launch cur = default_launch(kind, prec);
+    const int kind = metric->kind, prec = solver->precision, method = solver->method;
+    g_dev.tuned.erase(tune_key(kind, prec, method));
+    tartarus_launch cur = default_launch(kind, prec, method);
     int grid = 0;
-    if ((rc = resolve_launch(kind, prec, &cur, cur, grid))) return rc;
+    if ((rc = resolve_launch(kind, prec, method, &cur, cur, grid))) return rc;
     float best_ms = 0.f;
     if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;  // warm-up
     if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;
@@ -518,13 +525,13 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
             L.block_threads = b;
             L.blocks_per_cu = 0;
             int g2 = 0;
-            if (resolve_launch(kind, prec, &L, L, g2)) continue;
+            if (resolve_launch(kind, prec, method, &L, L, g2)) continue;
             float ms = 0.f;
             if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
             if (ms < best_ms) { best_ms = ms; cur = L; }
         }
         int occ = 0;
-        HIP_TRY(tartarus_occupancy(kind, prec, cur.block_threads, &occ));
+        HIP_TRY(tartarus_occupancy(kind, prec, method, cur.block_threads, &occ));
         for (int bpc = 1; bpc <= occ; ++bpc) {
             tartarus_launch L = cur;
             L.blocks_per_cu = bpc;
@@ -554,7 +561,7 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
             if (ms < best_ms) { best_ms = ms; cur = L; }
         }
     }
-    g_dev.tuned[kind * 2 + prec] = cur;
+    g_dev.tuned[tune_key(kind, prec, method)] = cur;
     *best = cur;
     return TARTARUS_OK;
 }
@@ -715,14 +722,14 @@ void rec_give(Server& S, double* p, long long n)
     }
 }
 
-int server_alloc(int prec)
+int server_alloc(int prec, int method)
 {
     Server& S = g_srv;
     HIP_TRY(hipSetDevice(g_dev.id));
     HIP_TRY(hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
     tartarus_launch L;
     int grid = 0;
-    int rc = resolve_launch(TARTARUS_METRIC_KERR, prec, nullptr, L, grid);
+    int rc = resolve_launch(TARTARUS_METRIC_KERR, prec, method, nullptr, L, grid);
     if (rc) return rc;
     S.grid = grid;
     S.block = L.block_threads;
@@ -903,7 +910,7 @@ int server_round(std::unique_lock<std::mutex>& lk)
     A.ndir = nd;
     A.remaining = S.dremaining;
     if (!fresh.empty()) HIP_TRY(tartarus_launch_setup(TARTARUS_METRIC_KERR, &A, S.stream));
-    HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, sv.precision, &A, S.grid, S.block, S.stream));
+    HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, sv.precision, sv.method, &A, S.grid, S.block, S.stream));
     HIP_TRY(hipMemcpyAsync(S.hremaining, S.dremaining, sizeof(unsigned int) * kMaxEntries, hipMemcpyDeviceToHost,
                            S.stream));
     HIP_TRY(hipMemcpyAsync(S.hhead, S.dhead, sizeof(unsigned long long), hipMemcpyDeviceToHost, S.stream));
@@ -932,7 +939,7 @@ void server_main()
     Server& S = g_srv;
     std::unique_lock<std::mutex> lk(S.mu);
     if (!S.dev_ready) {
-        int rc = server_alloc(S.solver.precision);
+        int rc = server_alloc(S.solver.precision, S.solver.method);
         if (rc) {
             S.dev_error = tartarus_last_error();
             S.running = false;

@@ -46,6 +46,60 @@ constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0, B5 
 constexpr double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0, E5 = -17253.0 / 339200.0,
                  E6 = 22.0 / 525.0, E7 = -1.0 / 40.0;
 
+// The two six-stage 5(4) pairs of Sec. 3.2 (Cash & Karp 1990, Fehlberg 1969):
+// stage matrix a, fifth-order weights b (propagated) and error weights
+// e = b - b* (b* the embedded fourth-order weights).  f(y5) closes each step
+// as the next step's first stage and the event interpolant's end slope.
+enum { METHOD_DP45 = 0, METHOD_CK45 = 1, METHOD_RKF45 = 2 };
+
+template <int M>
+struct Pair;
+
+template <>
+struct Pair<METHOD_CK45> {
+    static constexpr double a[6][5] = {{0, 0, 0, 0, 0},
+                                       {1.0 / 5.0, 0, 0, 0, 0},
+                                       {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0},
+                                       {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0},
+                                       {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0},
+                                       {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0,
+                                        253.0 / 4096.0}};
+    static constexpr double b[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+    static constexpr double e[6] = {37.0 / 378.0 - 2825.0 / 27648.0, 0.0, 250.0 / 621.0 - 18575.0 / 48384.0,
+                                    125.0 / 594.0 - 13525.0 / 55296.0, 0.0 - 277.0 / 14336.0,
+                                    512.0 / 1771.0 - 1.0 / 4.0};
+};
+
+template <>
+struct Pair<METHOD_RKF45> {
+    static constexpr double a[6][5] = {{0, 0, 0, 0, 0},
+                                       {1.0 / 4.0, 0, 0, 0, 0},
+                                       {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0},
+                                       {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0},
+                                       {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0},
+                                       {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+    static constexpr double b[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0};
+    static constexpr double e[6] = {16.0 / 135.0 - 25.0 / 216.0, 0.0, 6656.0 / 12825.0 - 1408.0 / 2565.0,
+                                    28561.0 / 56430.0 - 2197.0 / 4104.0, -9.0 / 50.0 + 1.0 / 5.0, 2.0 / 55.0};
+};
+
+// sum_j w[j] k[j] over the nonzero weights (known at compile time once
+// unrolled): the first term a product, the rest fused in index order.
+template <int N>
+__device__ __forceinline__ double weighted(const double (&w)[N], const double (&k)[N])
+{
+    double acc = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (w[j] != 0.0) {
+            acc = first ? w[j] * k[j] : fma(w[j], k[j], acc);
+            first = false;
+        }
+    }
+    return acc;
+}
+
 enum { CLS_ESCAPED = 0, CLS_CAPTURED = 1, CLS_FAILED = 2 };
 
 struct Ray {
@@ -499,6 +553,53 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
 #undef TT_E
 }
 
+// One attempted step of a six-stage pair (Cash-Karp or Fehlberg) with FP64
+// stages: the same outputs as stages64.
+template <int KIND, int M>
+__device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>& M_, double h, Deriv<double>& y5,
+                                             Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
+{
+    using P = Pair<M>;
+    const double a = R.a;
+    // component-wise stage derivatives kc[stage] for the dynamic components
+    double kt[6], kr[6], kth[6], kph[6], kpr[6], kpth[6];
+    kt[0] = R.k.t;
+    kr[0] = R.k.r;
+    kth[0] = R.k.th;
+    kph[0] = R.k.ph;
+    kpr[0] = R.k.pr;
+    kpth[0] = R.k.pth;
+#pragma unroll
+    for (int s = 1; s < 6; ++s) {
+        double w[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 5; ++j) w[j] = P::a[s][j];
+        Deriv<double> ks;
+        double Hd, cd;
+        M_.rhs(a, fma(h, weighted(w, kr), R.r), fma(h, weighted(w, kth), R.th), fma(h, weighted(w, kpr), R.pr),
+               fma(h, weighted(w, kpth), R.pth), R.pt, R.pph, ks, Hd, cd);
+        kt[s] = ks.t;
+        kr[s] = ks.r;
+        kth[s] = ks.th;
+        kph[s] = ks.ph;
+        kpr[s] = ks.pr;
+        kpth[s] = ks.pth;
+    }
+    y5.t = fma(h, weighted(P::b, kt), R.t);
+    y5.r = fma(h, weighted(P::b, kr), R.r);
+    y5.th = fma(h, weighted(P::b, kth), R.th);
+    y5.ph = fma(h, weighted(P::b, kph), R.ph);
+    y5.pr = fma(h, weighted(P::b, kpr), R.pr);
+    y5.pth = fma(h, weighted(P::b, kpth), R.pth);
+    M_.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+    e.t = h * weighted(P::e, kt);
+    e.r = h * weighted(P::e, kr);
+    e.th = h * weighted(P::e, kth);
+    e.ph = h * weighted(P::e, kph);
+    e.pr = h * weighted(P::e, kpr);
+    e.pth = h * weighted(P::e, kpth);
+}
+
 __device__ __forceinline__ double sq_ratio(double e, double y0, double y1, double atol, double rtol)
 {
     const double z = e * rcp64(fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
@@ -530,7 +631,7 @@ __device__ __forceinline__ double step_factor(double err, double fmx)
 }
 
 // One attempt; returns true when the ray has terminated (outputs written).
-template <int KIND, int PREC>
+template <int KIND, int PREC, int METHOD>
 __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
 {
     if ((long long)R.n_acc + R.n_rej >= A.max_steps) {
@@ -551,7 +652,10 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
             M.rhs(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth);
             R.k32 = 0;
         }
-        stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
+        if constexpr (METHOD == METHOD_DP45)
+            stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
+        else
+            stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
     }
     R.n_f32 += used32 ? 1 : 0;
     const double atol = A.atol, rtol = A.rtol;
@@ -681,13 +785,13 @@ __device__ __forceinline__ void count_done(const LaunchArgs& A, int& done)
 // SIMD is usually fastest once the event roots are left to the finishing pass
 // (a lone wavefront keeps the long rays' critical path short); a second gives
 // the short rays more throughput.  The autotuner picks between the two.
-template <int KIND, int PREC>
+template <int KIND, int PREC, int METHOD>
 struct WavesPerEU {
     static constexpr int value = 2;
 };
 
-template <int KIND, int PREC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<KIND, PREC>::value)))
+template <int KIND, int PREC, int METHOD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<KIND, PREC, METHOD>::value)))
 trace_persistent(LaunchArgs A)
 {
     MetricOps<KIND> M;
@@ -772,7 +876,7 @@ trace_persistent(LaunchArgs A)
             continue;
         }
         if (active) {
-            active = !ray_step<KIND, PREC>(R, A, M);
+            active = !ray_step<KIND, PREC, METHOD>(R, A, M);
             if (!active) {
                 done = R.job;
             } else if (A.slots && --budget == 0) {
@@ -997,23 +1101,39 @@ extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hi
     return hipGetLastError();
 }
 
-extern "C" hipError_t tartarus_launch_trace(int kind, int prec, const LaunchArgs* args, int grid, int block,
-                                            hipStream_t stream)
+// The integrator instance for (metric kind, precision, method); null if there
+// is none.  Mixed precision and the tabulated metric are provided with
+// Dormand-Prince only (a tabulated six-stage instance keeps all six stage
+// derivatives next to the table patch and spills heavily).
+static const void* trace_kernel_for(int kind, int prec, int method)
 {
-    if (kind == 0 && prec == 0)
-        hipLaunchKernelGGL((trace_persistent<0, 0>), dim3(grid), dim3(block), 0, stream, *args);
-    else if (kind == 0 && prec == 1)
-        hipLaunchKernelGGL((trace_persistent<0, 1>), dim3(grid), dim3(block), 0, stream, *args);
-    else if (kind == 1)
-        hipLaunchKernelGGL((trace_persistent<1, 0>), dim3(grid), dim3(block), 0, stream, *args);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (kind == 0 && prec == 0 && method == 0) return (const void*)trace_persistent<0, 0, 0>;
+    if (kind == 0 && prec == 0 && method == 1) return (const void*)trace_persistent<0, 0, 1>;
+    if (kind == 0 && prec == 0 && method == 2) return (const void*)trace_persistent<0, 0, 2>;
+    if (kind == 0 && prec == 1 && method == 0) return (const void*)trace_persistent<0, 1, 0>;
+    if (kind == 1 && prec == 0 && method == 0) return (const void*)trace_persistent<1, 0, 0>;
+    return nullptr;
 }
 
-// Shade jobs [job0, job0 + njobs), each with at most max_rays rays.
+extern "C" hipError_t tartarus_launch_trace(int kind, int prec, int method, const LaunchArgs* args, int grid,
+                                            int block, hipStream_t stream)
+{
+    const void* f = trace_kernel_for(kind, prec, method);
+    if (!f) return hipErrorInvalidValue;
+    void* params[] = {(void*)args};
+    return hipLaunchKernel(f, dim3(grid), dim3(block), params, 0, stream);
+}
+
+extern "C" hipError_t tartarus_occupancy(int kind, int prec, int method, int block, int* blocks_per_cu)
+{
+    const void* f = trace_kernel_for(kind, prec, method);
+    if (!f) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, 0);
+}
+
+// Finishing pass for jobs [job0, job0 + njobs), each with at most max_rays rays.
 extern "C" hipError_t tartarus_launch_finish(const LaunchArgs* args, int job0, int njobs, long long max_rays,
-                                            hipStream_t stream)
+                                             hipStream_t stream)
 {
     if (njobs <= 0 || max_rays <= 0) return hipSuccess;
     const long long bx = (max_rays + 255) / 256;
@@ -1021,13 +1141,4 @@ extern "C" hipError_t tartarus_launch_finish(const LaunchArgs* args, int job0, i
     hipLaunchKernelGGL(finish_kernel, dim3((unsigned)bx, (unsigned)njobs), dim3(256), 0, stream, args->jobs, args->jc,
                        job0);
     return hipGetLastError();
-}
-
-extern "C" hipError_t tartarus_occupancy(int kind, int prec, int block, int* blocks_per_cu)
-{
-    const void* f = nullptr;
-    if (kind == 0 && prec == 0) f = (const void*)trace_persistent<0, 0>;
-    else if (kind == 0 && prec == 1) f = (const void*)trace_persistent<0, 1>;
-    else f = (const void*)trace_persistent<1, 0>;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, 0);
 }

@@ -21,6 +21,7 @@ ESCAPED, CAPTURED, FAILED = 0, 1, 2
 METRIC_KERR, METRIC_TABLE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 ORDER_DEFAULT, ORDER_PIXEL, ORDER_COST = 0, 1, 2
+METHOD_DP45, METHOD_CK45, METHOD_RKF45 = 0, 1, 2
 
 
 class TartarusError(RuntimeError):
@@ -135,7 +136,7 @@ def make_disk(d: dict | None) -> Disk:
 
 def make_solver(s: dict, precision: int = PREC_FP64) -> Solver:
     return Solver(s["rtol"], s["atol"], s.get("h0_frac", 0.01), s.get("horizon_factor", 1.01),
-                  s["r_escape"], s.get("event_tol", 1e-12), s.get("max_steps", 1_000_000), precision, 0)
+                  s["r_escape"], s.get("event_tol", 1e-12), s.get("max_steps", 1_000_000), precision, s.get("method", 0))
 
 
 def make_launch(block_threads=0, blocks_per_cu=0, chunk=0, refill_min=0, order=0) -> Launch:

@@ -159,6 +159,24 @@ def test_more_cameras_than_the_lds_directory(T, orc):
         assert np.array_equal(gs["cls"], o["cls"]) and np.array_equal(gs["n_hits"], o["n_hits"])
 
 
+@pytest.mark.parametrize("method", [1, 2], ids=["ck45", "rkf45"])
+def test_six_stage_pairs_full_images(T, orc, method):
+    """Cash-Karp and Fehlberg (Sec. 3.2) on the Schwarzschild shadow and a ragged
+    Kerr image with the disk, against the oracle's same pair."""
+    w = W.WORKLOADS["schwarzschild_64"]
+    say("case schwarzschild_64 method", method)
+    g, o = full_image_parity(T, orc, w["a"], w["cameras"][0], w["disk"], dict(w["solver"], method=method))
+    assert np.mean(g["n_accept"] == o["n_accept"]) > 0.99
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=37, ny=29)
+    say("case kerr09 37x29 method", method)
+    g, o = full_image_parity(T, orc, w["a"], cam, w["disk"], dict(w["solver"], method=method))
+    assert (o["n_hits"] > 0).sum() > 50
+    # a different pair takes a different number of steps on the same image
+    d = gpu_trace(T, w["a"], cam, w["disk"], w["solver"])
+    assert not np.array_equal(d["n_accept"], g["n_accept"])
+
+
 def test_single_pixel_and_single_row(T, orc):
     w = W.WORKLOADS["kerr09_512"]
     for nx, ny in ((1, 1), (17, 1), (1, 5)):
