@@ -104,6 +104,8 @@ struct LaunchArgs {
     const unsigned int* order;
     // serving: rays still to finish, per job-table entry (null: not counted)
     unsigned int* remaining;
+    // tabulated metric interleaved by grid point (the integrator reads this)
+    const double* table_inter;
 };
 
 constexpr int SLOT_DOUBLES = 32;

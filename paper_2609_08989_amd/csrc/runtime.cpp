@@ -38,6 +38,7 @@ extern "C" hipError_t tartarus_launch_build_table(double a, int nr, int nth, dou
 extern "C" hipError_t tartarus_launch_order(const LaunchArgs* args, long long total, unsigned char* key,
                                             unsigned int* count, unsigned int* cursor, unsigned int* order,
                                             hipStream_t stream);
+extern "C" hipError_t tartarus_launch_table_interleave(const LaunchArgs* args, double* inter, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_fill_u64(unsigned long long* p, unsigned long long v, long long n,
                                                hipStream_t stream);
@@ -83,6 +84,8 @@ struct Slot {
     size_t ord_cap = 0;                  // bytes
     double* rec = nullptr;               // per-ray records for the finishing pass
     size_t rec_cap = 0;                  // rays
+    double* inter = nullptr;             // tabulated metric interleaved by grid point
+    size_t inter_cap = 0;                // doubles
     hipEvent_t ev = nullptr;
     bool pending = false;
 };
@@ -368,6 +371,18 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
     A.total_rays = per * ncams;
     A.head = S->head;
     HIP_TRY(tartarus_launch_setup(kind, &A, stream));
+    if (kind == TARTARUS_METRIC_TABLE) {
+        const size_t need = (size_t)metric->nr * metric->nth * 20;
+        if (need > S->inter_cap) {
+            if (S->inter) (void)hipFree(S->inter);
+            S->inter = nullptr;
+            S->inter_cap = 0;
+            HIP_TRY(hipMalloc(&S->inter, need * sizeof(double)));
+            S->inter_cap = need;
+        }
+        HIP_TRY(tartarus_launch_table_interleave(&A, S->inter, stream));
+        A.table_inter = S->inter;
+    }
     const long long n = A.total_rays;
     const bool cost = n <= 0xffffffffll &&
                       (L.order == TARTARUS_ORDER_COST || (L.order == TARTARUS_ORDER_DEFAULT && n >= kCostOrderMin));
@@ -584,6 +599,7 @@ extern "C" int tartarus_shutdown(void)
         if (S.head) (void)hipFree(S.head);
         if (S.ord) (void)hipFree(S.ord);
         if (S.rec) (void)hipFree(S.rec);
+        if (S.inter) (void)hipFree(S.inter);
         if (S.ev) (void)hipEventDestroy(S.ev);
         S = Slot();
     }

@@ -7,6 +7,11 @@
 // r_k = exp(ln r_min + k du), l over theta_l = l dth, dth = pi / (nth - 1),
 // last index (f, df/dr, df/dth, d2f/dr dth).  The two azimuthal components are
 // tabulated divided by sin^2(theta) so that they stay smooth at the axis.
+//
+// The integrator reads a copy the library interleaves by grid point,
+// [k][l][c][4]: the five components of a node share 160 contiguous bytes, so
+// the 2 x 2 nodes of a cell are two 320-byte runs instead of ten 64-byte pieces
+// on five planes 4 MiB apart.  The values are the caller's, only reordered.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,7 +21,8 @@
 namespace tartarus {
 
 struct TableView {
-    const double* tab;
+    const double* tab;       // [c][k][l][4] (the caller's layout)
+    const double* inter;     // [k][l][c][4] (interleaved copy), or null
     int nr, nth;
     double u0, du, idu, dth, idth;
 };
@@ -25,6 +31,7 @@ __host__ __device__ inline TableView make_table_view(const double* tab, int nr, 
 {
     TableView v;
     v.tab = tab;
+    v.inter = nullptr;
     v.nr = nr;
     v.nth = nth;
     v.u0 = log(r_min);
@@ -57,7 +64,8 @@ __device__ __forceinline__ Hb hermite_basis(double x)
 }
 
 // Interpolated metric: g[5] covariant components, gr[5] = d/dr, gt[5] = d/dtheta.
-template <bool WITH_DERIVS>
+// INTER: read the interleaved copy (T.inter), else the caller's layout.
+template <bool WITH_DERIVS, bool INTER>
 __device__ __forceinline__ void table_metric(const TableView& T, double r, double th, double g[5], double gr[5],
                                              double gt[5])
 {
@@ -73,13 +81,14 @@ __device__ __forceinline__ void table_metric(const TableView& T, double r, doubl
     const double rk0 = exp(uk), rk1 = exp(fma((double)(k + 1), T.du, T.u0));
     const double sdu0 = rk0 * T.du, sdu1 = rk1 * T.du;
     const size_t plane = (size_t)T.nr * T.nth * 4;
-    const double* base = T.tab + ((size_t)k * T.nth + l) * 4;
+    const double* base = INTER ? T.inter + ((size_t)k * T.nth + l) * 20 : T.tab + ((size_t)k * T.nth + l) * 4;
+    const size_t cstep = INTER ? 4 : plane, lstep = INTER ? 20 : 4, kstep = (size_t)T.nth * lstep;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        const double* e00 = base + c * plane;          // (k, l)
-        const double* e01 = e00 + 4;                   // (k, l+1)
-        const double* e10 = e00 + (size_t)T.nth * 4;   // (k+1, l)
-        const double* e11 = e10 + 4;                   // (k+1, l+1)
+        const double* e00 = base + c * cstep;          // (k, l)
+        const double* e01 = e00 + lstep;               // (k, l+1)
+        const double* e10 = e00 + kstep;               // (k+1, l)
+        const double* e11 = e10 + lstep;               // (k+1, l+1)
         const double4 c00 = *reinterpret_cast<const double4*>(e00);
         const double4 c01 = *reinterpret_cast<const double4*>(e01);
         const double4 c10 = *reinterpret_cast<const double4*>(e10);
@@ -120,14 +129,15 @@ __device__ __forceinline__ void table_metric(const TableView& T, double r, doubl
     g[4] *= s2;
 }
 
-// Generic right-hand side of Eqs. (2)-(3) for a metric of the form of Eq. (6):
+// Generic right-hand side of Eqs. (2)-(3) for a metric of the form of Eq. (6),
+// on the interleaved copy (T.inter must be set):
 // dx^mu = g^{mu nu} p_nu and dp_mu = 1/2 (d_mu g_ab) dx^a dx^b (the same as
 // -1/2 (d_mu g^{ab}) p_a p_b, since d g^{-1} = -g^{-1} (d g) g^{-1}).
 __device__ __forceinline__ void table_rhs64(const TableView& T, double r, double th, double pr, double pth,
                                             double pt, double pph, Deriv<double>& d, double& H, double& cth)
 {
     double g[5], gr[5], gt[5];
-    table_metric<true>(T, r, th, g, gr, gt);
+    table_metric<true, true>(T, r, th, g, gr, gt);
     const double idet = rcp64(fma(g[0], g[4], -g[1] * g[1]));
     const double Gtt = g[4] * idet, Gtp = -g[1] * idet, Gpp = g[0] * idet;
     const double Grr = rcp64(g[2]), Ghh = rcp64(g[3]);

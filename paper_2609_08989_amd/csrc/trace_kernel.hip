@@ -134,7 +134,7 @@ struct MetricOps {
             kerr_metric64(a, r, th, g);
         } else {
             double gr[5], gt[5];
-            table_metric<false>(T, r, th, g, gr, gt);
+            table_metric<false, false>(T, r, th, g, gr, gt);
         }
     }
 };
@@ -795,7 +795,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesP
 trace_persistent(LaunchArgs A)
 {
     MetricOps<KIND> M;
-    if (KIND == 1) M.T = make_table_view(A.table, A.nr, A.nth, A.tab_r_min, A.tab_r_max);
+    if (KIND == 1) {
+        M.T = make_table_view(A.table, A.nr, A.nth, A.tab_r_min, A.tab_r_max);
+        M.T.inter = A.table_inter;
+    }
     // job directory in LDS
     __shared__ long long s_begin[kLdsJobs];
     __shared__ int s_job[kLdsJobs];
@@ -1140,5 +1143,28 @@ extern "C" hipError_t tartarus_launch_finish(const LaunchArgs* args, int job0, i
     if (bx > 0x7fffffffll || njobs > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(finish_kernel, dim3((unsigned)bx, (unsigned)njobs), dim3(256), 0, stream, args->jobs, args->jc,
                        job0);
+    return hipGetLastError();
+}
+
+// Interleave the caller's table by grid point for the integrator (table.hpp):
+// one thread per (node, component), 4 doubles each.
+__global__ void table_interleave_kernel(const double* table, long long nodes, double* inter)
+{
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= nodes * 5) return;
+    const long long node = i / 5;
+    const int c = (int)(i - node * 5);
+    const double4 v = *reinterpret_cast<const double4*>(table + ((size_t)c * nodes + node) * 4);
+    *reinterpret_cast<double4*>(inter + (size_t)i * 4) = v;
+}
+
+extern "C" hipError_t tartarus_launch_table_interleave(const LaunchArgs* args, double* inter, hipStream_t stream)
+{
+    const long long nodes = (long long)args->nr * args->nth;
+    if (nodes <= 0) return hipErrorInvalidValue;
+    const long long blocks = (nodes * 5 + 255) / 256;
+    if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(table_interleave_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, args->table, nodes,
+                       inter);
     return hipGetLastError();
 }
