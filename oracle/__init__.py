@@ -88,6 +88,8 @@ def lib():
         L.or_dp45_fixed.argtypes = [C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
         L.or_rk_tableau.argtypes = [C.c_int, dp, dp, dp, dp]
         L.or_rk_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
+        L.or_gbs_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
+        L.or_gbs_columns.restype = C.c_int
         L.or_hermite.argtypes = [C.c_double] * 6
         L.or_hermite.restype = C.c_double
         L.or_bisect_count.argtypes = [C.c_double, C.c_double]
@@ -212,7 +214,8 @@ def bisect_count(h, tol): return lib().or_bisect_count(h, tol)
 def max_threads(): return lib().or_max_threads()
 
 
-METHODS = {"dp45": 0, "ck45": 1, "rkf45": 2}
+METHODS = {"dp45": 0, "ck45": 1, "rkf45": 2, "gbs": 3}
+RK_METHODS = {"dp45": 0, "ck45": 1, "rkf45": 2}
 
 
 def dp45_tableau():
@@ -230,21 +233,40 @@ def dp45_fixed(f, y0, h: float, nsteps: int):
     return rk_fixed(0, f, y0, h, nsteps)
 
 
-def rk_fixed(method: int, f, y0, h: float, nsteps: int):
-    """Fixed-step steps of a 5(4) pair on y' = f(y) (f: numpy array -> numpy array); returns
-    (y, last error vector)."""
-    n = len(y0)
-
+def _user_rhs(f):
     def cb(yp, dyp, nn):
         y = np.ctypeslib.as_array(yp, shape=(nn,)).copy()
         d = f(y)
         for k in range(nn):
             dyp[k] = float(d[k])
+    return USER_RHS(cb)
 
-    cfun = USER_RHS(cb)
+
+def rk_fixed(method: int, f, y0, h: float, nsteps: int):
+    """Fixed-step steps of a 5(4) pair on y' = f(y) (f: numpy array -> numpy array); returns
+    (y, last error vector)."""
+    n = len(y0)
+    cfun = _user_rhs(f)
     y = np.ascontiguousarray(y0, dtype=np.float64).copy()
     e = np.zeros(n)
     lib().or_rk_fixed(method, n, cfun, _dptr(y), h, nsteps, _dptr(e))
+    return y, e
+
+
+def gbs_columns() -> int:
+    """Extrapolation columns K the ray tracer uses with method 3."""
+    return lib().or_gbs_columns()
+
+
+def gbs_fixed(K: int, f, y0, h: float, nsteps: int):
+    """Fixed macro-steps of Gragg-Bulirsch-Stoer extrapolation with K columns
+    (2 <= K <= 8) on y' = f(y); returns (y, last error vector)."""
+    assert 2 <= K <= 8
+    n = len(y0)
+    cfun = _user_rhs(f)
+    y = np.ascontiguousarray(y0, dtype=np.float64).copy()
+    e = np.zeros(n)
+    lib().or_gbs_fixed(K, n, cfun, _dptr(y), h, nsteps, _dptr(e))
     return y, e
 
 

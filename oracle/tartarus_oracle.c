@@ -14,8 +14,10 @@
  *     ZAMO tetrad projection at the observer (t=0, r=D, theta=iota, phi=0).
  *   - Sec. 2.3, Eqs. (11)-(12): Page-Thorne flux and the cubic roots.
  *   - Sec. 2.4, Eqs. (13)-(16): redshift g and I_obs = g^4 I_em.
- *   - Sec. 3.2: Dormand-Prince 5(4) pair with local extrapolation and
- *     embedded error estimate; horizon / escape / equatorial-disk events
+ *   - Sec. 3.2: Dormand-Prince, Cash-Karp and Fehlberg 5(4) pairs with local
+ *     extrapolation and embedded error estimate; Gragg-Bulirsch-Stoer
+ *     modified-midpoint extrapolation with error-controlled macro-steps;
+ *     horizon / escape / equatorial-disk events
  *     refined by bisection on the step's cubic Hermite interpolant to about
  *     1e-12 in the affine parameter.
  *   - Sec. 4.1, Eq. (17): the constraint residual |H| at every accepted step.
@@ -23,7 +25,8 @@
  * Readings where the paper is silent (kept identical on the HIP side, each
  * written out where it is used): the tetrad's e_(t)^phi component, the pixel
  * grid, the sign flip used for backward tracing, the step-size controller,
- * the failure limits, the event rules and the bisection count, the emitter's
+ * the failure limits, the event rules and the bisection count, the
+ * extrapolation's substep sequence, column count and error estimate, the emitter's
  * Keplerian angular velocity, the a = 0 guard in the flux sum.
  *
  * The metric derivatives come from hyper-dual arithmetic (exact first and
@@ -491,6 +494,80 @@ void or_dp45_fixed(int n, or_user_rhs f, double* y, double h, int nsteps, double
 }
 
 /* ------------------------------------------------------------------ */
+/* Gragg-Bulirsch-Stoer extrapolation (Sec. 3.2): a macro-step of size  */
+/* H is covered K times by Gragg's modified midpoint rule, the j-th time */
+/* with n_j = 2j equal substeps; each result T[j][1] has an error        */
+/* expansion in even powers of the substep H/n_j, and Richardson         */
+/* extrapolation to zero substep in (H/n)^2 fills the tableau            */
+/* (Aitken-Neville form)                                                 */
+/*   T[j][k+1] = T[j][k] + (T[j][k] - T[j-1][k]) / ((n_j/n_{j-k})^2 - 1). */
+/* The diagonal T[K][K] propagates the solution and the difference to    */
+/* T[K][K-1] is the error estimate driving the macro-step control.       */
+/* ------------------------------------------------------------------ */
+#define GBS_KMAX 8
+
+static int gbs_substeps(int j) { return 2 * j; }
+
+/* Gragg's modified midpoint rule: m substeps of size hs = H/m from y, where
+ * k1 = f(y):  z_0 = y,  z_1 = z_0 + hs f(z_0),  z_{i+1} = z_{i-1} + 2 hs f(z_i),
+ * followed by the smoothing step  (z_m + z_{m-1} + hs f(z_m)) / 2. */
+static void modified_midpoint(int n, rhs_fn f, void* ctx, const double* y, const double* k1, double H, int m,
+                              double* out)
+{
+    double hs = H / (double)m;
+    double zprev[16], z[16], znext[16], dz[16];
+    for (int d = 0; d < n; ++d) {
+        zprev[d] = y[d];
+        z[d] = y[d] + hs * k1[d];
+    }
+    for (int i = 1; i < m; ++i) {
+        f(ctx, z, dz);
+        for (int d = 0; d < n; ++d) znext[d] = zprev[d] + 2.0 * hs * dz[d];
+        for (int d = 0; d < n; ++d) { zprev[d] = z[d]; z[d] = znext[d]; }
+    }
+    f(ctx, z, dz);
+    for (int d = 0; d < n; ++d) out[d] = 0.5 * (zprev[d] + z[d] + hs * dz[d]);
+}
+
+/* One macro-step with K columns from y (k1 = f(y)): writes T[K][K], the error
+ * vector T[K][K] - T[K][K-1] and f(T[K][K]). */
+static void gbs_attempt(int K, int n, rhs_fn f, void* ctx, const double* y, const double* k1, double H,
+                        double* ynew, double* err, double* knew)
+{
+    double T[GBS_KMAX][GBS_KMAX][16];
+    for (int j = 1; j <= K; ++j) {
+        modified_midpoint(n, f, ctx, y, k1, H, gbs_substeps(j), T[j - 1][0]);
+        for (int k = 1; k < j; ++k) {
+            double ratio = (double)gbs_substeps(j) / (double)gbs_substeps(j - k);
+            double den = ratio * ratio - 1.0;
+            for (int d = 0; d < n; ++d)
+                T[j - 1][k][d] = T[j - 1][k - 1][d] + (T[j - 1][k - 1][d] - T[j - 2][k - 1][d]) / den;
+        }
+    }
+    for (int d = 0; d < n; ++d) {
+        ynew[d] = T[K - 1][K - 1][d];
+        err[d] = T[K - 1][K - 1][d] - T[K - 1][K - 2][d];
+    }
+    f(ctx, ynew, knew);
+}
+
+/* Columns of the extrapolation used to trace rays (orders 2K and 2K - 2). */
+int or_gbs_columns(void) { return OR_GBS_COLUMNS; }
+
+/* Test hook: fixed macro-steps with K columns (2 <= K <= 8) on a user ODE. */
+void or_gbs_fixed(int K, int n, or_user_rhs f, double* y, double h, int nsteps, double* last_err)
+{
+    struct user_ctx u = {f, n};
+    double k1[16], yn[16], e[16], kn[16];
+    if (K < 2 || K > GBS_KMAX) return;
+    f(y, k1, n);
+    for (int s = 0; s < nsteps; ++s) {
+        gbs_attempt(K, n, user_tramp, &u, y, k1, h, yn, e, kn);
+        for (int d = 0; d < n; ++d) { y[d] = yn[d]; k1[d] = kn[d]; last_err[d] = e[d]; }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Dense output and event location (Sec. 3.2).                          */
 /* ------------------------------------------------------------------ */
 
@@ -600,6 +677,9 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
     int nrec = 0;
     if (rec && nrec < rec_cap) { memcpy(rec, y, sizeof(y)); rec_l[0] = 0.0; nrec = 1; }
 
+    /* controller exponent -1/(p+1) with p the order of the error estimate:
+     * 4 for the Runge-Kutta pairs, 2K - 2 for the extrapolation */
+    double expo = sv->method == OR_METHOD_GBS ? -1.0 / (2.0 * OR_GBS_COLUMNS - 1.0) : -0.2;
     double H0 = fabs(hamiltonian_m(m, y));
     out->h_drift = H0;
     out->h_gate = y[R_] >= r_gate ? H0 : 0.0;
@@ -607,7 +687,10 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
 
     for (;;) {
         if ((int64_t)out->n_accept + out->n_reject >= sv->max_steps) break;
-        rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
+        if (sv->method == OR_METHOD_GBS)
+            gbs_attempt(OR_GBS_COLUMNS, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
+        else
+            rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
         /* RMS error norm over all eight components */
         double acc = 0.0;
         for (int d = 0; d < NSTATE; ++d) {
@@ -619,7 +702,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
         if (!(err <= 1.0)) {
             /* rejected (a NaN or infinite error also lands here) */
             out->n_reject++;
-            double fac = isnan(err) ? 0.2 : fmax(0.2, 0.9 * pow(err, -0.2));
+            double fac = isnan(err) ? 0.2 : fmax(0.2, 0.9 * pow(err, expo));
             h *= fac;
             rejected_prev = 1;
             if (h < 1e-14 * fmax(1.0, fabs(lambda))) break;
@@ -702,10 +785,10 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
             return;
         }
 
-        /* elementary controller: safety 0.9, exponent -1/5, factor in [0.2, 10],
-         * no growth on the step right after a rejection */
+        /* elementary controller: safety 0.9, factor in [0.2, 10], no growth
+         * on the step right after a rejection */
         double fmax_ = rejected_prev ? 1.0 : 10.0;
-        double fac = err == 0.0 ? fmax_ : fmin(fmax_, fmax(0.2, 0.9 * pow(err, -0.2)));
+        double fac = err == 0.0 ? fmax_ : fmin(fmax_, fmax(0.2, 0.9 * pow(err, expo)));
         lambda += h;
         for (int d = 0; d < NSTATE; ++d) { y[d] = y5[d]; k1[d] = k7[d]; }
         h *= fac;

@@ -38,7 +38,10 @@ typedef struct {
     int max_hits;          /* 0..3; 0 = no disk                                      */
 } or_disk;
 
-/* method: 0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg 5(4) pair (Sec. 3.2). */
+/* method: 0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg 5(4) pair, 3 Gragg-
+ * Bulirsch-Stoer extrapolation with OR_GBS_COLUMNS columns (Sec. 3.2). */
+#define OR_METHOD_GBS 3
+#define OR_GBS_COLUMNS 6
 typedef struct {
     double rtol, atol, h0_frac, horizon_factor, r_escape, event_tol;
     int64_t max_steps;

@@ -176,6 +176,50 @@ def test_rk_convergence_order_five(orc, method):
     assert 24 < ests[0] / ests[1] < 44 and 24 < ests[1] / ests[2] < 44  # embedded estimate ~ h^5
 
 
+# ------------------------------------------------- Gragg-Bulirsch-Stoer
+@pytest.mark.parametrize("K", [2, 3, 4, 5, 6])
+def test_gbs_exact_on_polynomials_of_degree_2k_minus_1(orc, K):
+    """On y' = p(t) the smoothed modified midpoint rule is the composite trapezoid
+    rule, whose error expands in even powers of the substep; K columns of
+    extrapolation in h^2 remove K - 1 of those terms, so one macro-step is exact
+    (to rounding) for deg p <= 2K - 1 and not for deg p = 2K."""
+    rng = np.random.default_rng(K)
+    t0, H = 0.3, 0.9
+    for deg, exact_expected in ((2 * K - 1, True), (2 * K, False)):
+        co = rng.normal(size=deg + 1)
+        f = lambda y: np.array([1.0, np.polyval(co, y[0])])
+        y, e = orc.gbs_fixed(K, f, [t0, 0.0], H, 1)
+        P = np.polyint(co)
+        exact = np.polyval(P, t0 + H) - np.polyval(P, t0)
+        if exact_expected:
+            assert abs(y[1] - exact) < 1e-13 * max(1.0, abs(exact))
+        else:
+            assert abs(y[1] - exact) > 1e-12
+        assert y[0] == pytest.approx(t0 + H, abs=1e-13)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_gbs_convergence_order_2k(orc, K):
+    """The diagonal entry T[K][K] converges with order 2K; the error estimate
+    T[K][K] - T[K][K-1] (the error of the order 2K - 2 entry) with order 2K - 1."""
+    f = lambda y: np.array([y[1], -y[0]])
+    T = 2.0
+    errs, ests = [], []
+    for N in (4, 8, 16):
+        y, e = orc.gbs_fixed(K, f, [1.0, 0.0], T / N, N)
+        errs.append(np.hypot(y[0] - math.cos(T), y[1] + math.sin(T)))
+        ests.append(np.abs(e).max())
+    want = 2.0 ** (2 * K)
+    assert 0.85 * want < errs[0] / errs[1] < 1.15 * want
+    assert 0.85 * want < errs[1] / errs[2] < 1.15 * want
+    west = 2.0 ** (2 * K - 1)
+    assert 0.7 * west < ests[1] / ests[2] < 1.3 * west
+
+
+def test_gbs_columns_used_for_rays(orc):
+    assert orc.gbs_columns() == 6
+
+
 # ----------------------------------------------------------------- events
 def test_hermite_exact_on_cubics(orc):
     rng = np.random.default_rng(3)
