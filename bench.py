@@ -325,6 +325,21 @@ def main():
             legs[f"{mname}_rtol1e-8"] = {"rays_per_s": n * args.steps / wl, "kernel_ms": km,
                                          "attempts_per_ray": float(attl.mean()),
                                          "failed_rays": int((ol["cls"] == 2).sum())}
+        # Gragg-Bulirsch-Stoer (Sec. 3.2) beside Dormand-Prince: at the config and
+        # gate tolerances, and at rtol 1e-12 where its order-12 macro-steps pay
+        for mname, sv in (("gbs_rtol1e-8", dict(w["solver"], method=T.METHOD_GBS)),
+                          ("gbs_gate", dict(gate_solver, method=T.METHOD_GBS)),
+                          ("gbs_rtol1e-12", dict(w["solver"], rtol=1e-12, atol=1e-14, method=T.METHOD_GBS)),
+                          ("fp64_rtol1e-12", dict(w["solver"], rtol=1e-12, atol=1e-14))):
+            la = (metric, cams, disk, T.make_solver(sv, T.PREC_FP64))
+            log("bench: leg", mname)
+            wl, km = time_leg(T, torch, la, out, args.steps, args.warmup)
+            ol = T.to_numpy(out)
+            attl = ol["n_accept"] + ol["n_reject"]
+            legs[mname] = {"rays_per_s": n * args.steps / wl, "kernel_ms": km,
+                           "attempts_per_ray": float(attl.mean()),
+                           "h_gate_max": float(ol["h_gate"][ol["cls"] != 2].max()),
+                           "failed_rays": int((ol["cls"] == 2).sum())}
         legs.update(workload_legs(T, torch, W, {}))
         legs["mixed_over_fp64_same_rtol"] = legs["mixed_rtol1e-8"]["rays_per_s"] / legs["fp64_rtol1e-8"]["rays_per_s"]
         legs["mixed_rtol1e-8_over_fp64_gate"] = legs["mixed_rtol1e-8"]["rays_per_s"] / value

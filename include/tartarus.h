@@ -114,12 +114,23 @@ typedef struct {
  * (attempted steps, accepted + rejected).  precision: TARTARUS_PREC_FP64, or
  * TARTARUS_PREC_MIXED (Runge-Kutta stages evaluated in FP32 in the far field;
  * state sums, error norm, controller, events and shading stay FP64).
- * method: the embedded 5(4) pair, TARTARUS_METHOD_DP45 (Dormand-Prince),
- * TARTARUS_METHOD_CK45 (Cash-Karp) or TARTARUS_METHOD_RKF45 (Fehlberg); each
- * propagates the fifth-order solution and controls the step with the embedded
- * fourth-order estimate (Sec. 3.2).  Mixed precision and the tabulated metric
- * need DP45. */
-enum { TARTARUS_METHOD_DP45 = 0, TARTARUS_METHOD_CK45 = 1, TARTARUS_METHOD_RKF45 = 2 };
+ * method (Sec. 3.2): an embedded 5(4) pair, TARTARUS_METHOD_DP45
+ * (Dormand-Prince), TARTARUS_METHOD_CK45 (Cash-Karp) or TARTARUS_METHOD_RKF45
+ * (Fehlberg), each propagating the fifth-order solution with the step
+ * controlled by the embedded fourth-order estimate; or TARTARUS_METHOD_GBS,
+ * Gragg-Bulirsch-Stoer extrapolation: per macro-step six modified-midpoint
+ * sweeps with 2, 4, ..., 12 substeps, Richardson extrapolation in h^2 to order
+ * 12, the difference to the order-10 entry as error estimate (42 right-hand
+ * sides per attempt, against 6 for a pair).  For every method, h0_frac,
+ * max_steps and the error norm keep their meaning (an attempt is one
+ * macro-step), and events are located on the cubic Hermite interpolant of the
+ * accepted step.  Mixed precision and the tabulated metric need DP45. */
+enum {
+    TARTARUS_METHOD_DP45 = 0,
+    TARTARUS_METHOD_CK45 = 1,
+    TARTARUS_METHOD_RKF45 = 2,
+    TARTARUS_METHOD_GBS = 3
+};
 typedef struct {
     double rtol, atol, h0_frac, horizon_factor, r_escape, event_tol;
     int64_t max_steps;

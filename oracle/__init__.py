@@ -16,17 +16,23 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tartarus_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with FMA contraction: a second correct FP64 rounding of
+# the same arithmetic, used to measure how far rounding alone moves a result.
+_LIB_FMA = os.path.join(_HERE, "liboracle_fma.so")
 
 ESCAPED, CAPTURED, FAILED = 0, 1, 2
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with plain IEEE semantics (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c11",
-               "-D_DEFAULT_SOURCE", "-Wall", "-shared", "-fPIC", _SRC, "-o", _LIB, "-lm"]
+def build(force: bool = True, fma: bool = False) -> str:
+    """Compile the oracle with plain IEEE semantics (no fast-math, no FMA
+    contraction); ``fma=True`` builds the rounding variant with a*b+c fused."""
+    out = _LIB_FMA if fma else _LIB
+    if force or not os.path.exists(out):
+        contract = ["-ffp-contract=fast", "-mfma"] if fma else ["-ffp-contract=off"]
+        cmd = ["gcc", "-O2", "-fno-fast-math", *contract, "-fopenmp", "-std=c11",
+               "-D_DEFAULT_SOURCE", "-Wall", "-shared", "-fPIC", _SRC, "-o", out, "-lm"]
         subprocess.run(cmd, check=True)
-    return _LIB
+    return out
 
 
 class Metric(C.Structure):
@@ -60,49 +66,61 @@ _lib = None
 USER_RHS = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int)
 
 
-def lib():
-    global _lib
+_lib_fma = None
+
+
+def lib(fma: bool = False):
+    global _lib, _lib_fma
+    if fma:
+        if _lib_fma is None:
+            if not os.path.exists(_LIB_FMA):
+                build(fma=True)
+            _lib_fma = _declare(C.CDLL(_LIB_FMA))
+        return _lib_fma
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
-        dp = C.POINTER(C.c_double)
-        L.or_trace.argtypes = [C.POINTER(Metric), C.POINTER(Camera), C.c_int, C.POINTER(Disk),
-                               C.POINTER(Solver), C.POINTER(C.c_int64), C.c_int64,
-                               C.POINTER(Outputs), C.c_int]
-        L.or_hamiltonian.argtypes = [C.POINTER(Metric), dp]
-        L.or_hamiltonian.restype = C.c_double
-        L.or_rhs.argtypes = [C.POINTER(Metric), dp, dp]
-        L.or_metric_eval.argtypes = [C.POINTER(Metric), C.c_double, C.c_double, dp, dp, dp]
-        L.or_kerr_smooth_components.argtypes = [C.c_double, C.c_double, C.c_double, dp]
-        L.or_initial_state.argtypes = [C.POINTER(Metric), C.POINTER(Camera), C.c_int, C.c_int, dp]
-        L.or_horizon.argtypes = [C.c_double]
-        L.or_horizon.restype = C.c_double
-        L.or_isco.argtypes = [C.c_double]
-        L.or_isco.restype = C.c_double
-        L.or_nt_flux.argtypes = [C.c_double] * 4
-        L.or_nt_flux.restype = C.c_double
-        L.or_redshift.argtypes = [C.c_double] * 4
-        L.or_redshift.restype = C.c_double
-        L.or_dp45_tableau.argtypes = [dp, dp, dp, dp]
-        L.or_dp45_fixed.argtypes = [C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
-        L.or_rk_tableau.argtypes = [C.c_int, dp, dp, dp, dp]
-        L.or_rk_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
-        L.or_gbs_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
-        L.or_gbs_columns.restype = C.c_int
-        L.or_hermite.argtypes = [C.c_double] * 6
-        L.or_hermite.restype = C.c_double
-        L.or_bisect_count.argtypes = [C.c_double, C.c_double]
-        L.or_bisect_count.restype = C.c_int
-        L.or_build_kerr_table.argtypes = [C.c_double, C.c_int, C.c_int, C.c_double, C.c_double, dp]
-        L.or_max_threads.restype = C.c_int
-        L.or_trace_path.argtypes = [C.POINTER(Metric), dp, C.c_double, C.POINTER(Disk), C.POINTER(Solver),
-                                    dp, dp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
-        L.or_rk4_step.argtypes = [C.POINTER(Metric), dp, C.c_double, dp]
-        L.or_rk4_run.argtypes = [C.POINTER(Metric), dp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int]
-        L.or_rk4_run.restype = C.c_int
-        _lib = L
+        _lib = _declare(C.CDLL(_LIB))
     return _lib
+
+
+def _declare(L):
+    dp = C.POINTER(C.c_double)
+    L.or_trace.argtypes = [C.POINTER(Metric), C.POINTER(Camera), C.c_int, C.POINTER(Disk),
+                           C.POINTER(Solver), C.POINTER(C.c_int64), C.c_int64,
+                           C.POINTER(Outputs), C.c_int]
+    L.or_hamiltonian.argtypes = [C.POINTER(Metric), dp]
+    L.or_hamiltonian.restype = C.c_double
+    L.or_rhs.argtypes = [C.POINTER(Metric), dp, dp]
+    L.or_metric_eval.argtypes = [C.POINTER(Metric), C.c_double, C.c_double, dp, dp, dp]
+    L.or_kerr_smooth_components.argtypes = [C.c_double, C.c_double, C.c_double, dp]
+    L.or_initial_state.argtypes = [C.POINTER(Metric), C.POINTER(Camera), C.c_int, C.c_int, dp]
+    L.or_horizon.argtypes = [C.c_double]
+    L.or_horizon.restype = C.c_double
+    L.or_isco.argtypes = [C.c_double]
+    L.or_isco.restype = C.c_double
+    L.or_nt_flux.argtypes = [C.c_double] * 4
+    L.or_nt_flux.restype = C.c_double
+    L.or_redshift.argtypes = [C.c_double] * 4
+    L.or_redshift.restype = C.c_double
+    L.or_dp45_tableau.argtypes = [dp, dp, dp, dp]
+    L.or_dp45_fixed.argtypes = [C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
+    L.or_rk_tableau.argtypes = [C.c_int, dp, dp, dp, dp]
+    L.or_rk_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
+    L.or_gbs_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
+    L.or_gbs_columns.restype = C.c_int
+    L.or_hermite.argtypes = [C.c_double] * 6
+    L.or_hermite.restype = C.c_double
+    L.or_bisect_count.argtypes = [C.c_double, C.c_double]
+    L.or_bisect_count.restype = C.c_int
+    L.or_build_kerr_table.argtypes = [C.c_double, C.c_int, C.c_int, C.c_double, C.c_double, dp]
+    L.or_max_threads.restype = C.c_int
+    L.or_trace_path.argtypes = [C.POINTER(Metric), dp, C.c_double, C.POINTER(Disk), C.POINTER(Solver),
+                                dp, dp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
+    L.or_rk4_step.argtypes = [C.POINTER(Metric), dp, C.c_double, dp]
+    L.or_rk4_run.argtypes = [C.POINTER(Metric), dp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int]
+    L.or_rk4_run.restype = C.c_int
+    return L
 
 
 def _dptr(a: np.ndarray):
@@ -148,9 +166,11 @@ def alloc_outputs(n: int) -> dict:
     return o
 
 
-def trace(metric: Metric, cameras, disk: Disk, solver: Solver, ray_ids=None, threads: int = 0) -> dict:
-    """Trace rays; ``cameras`` is one Camera or a list (all with the same nx, ny)."""
-    L = lib()
+def trace(metric: Metric, cameras, disk: Disk, solver: Solver, ray_ids=None, threads: int = 0,
+          fma: bool = False) -> dict:
+    """Trace rays; ``cameras`` is one Camera or a list (all with the same nx, ny).
+    ``fma=True`` runs the FMA-contracted build of the same source."""
+    L = lib(fma)
     if isinstance(cameras, Camera):
         cameras = [cameras]
     cams = (Camera * len(cameras))(*cameras)

@@ -50,7 +50,7 @@ constexpr double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0, 
 // stage matrix a, fifth-order weights b (propagated) and error weights
 // e = b - b* (b* the embedded fourth-order weights).  f(y5) closes each step
 // as the next step's first stage and the event interpolant's end slope.
-enum { METHOD_DP45 = 0, METHOD_CK45 = 1, METHOD_RKF45 = 2 };
+enum { METHOD_DP45 = 0, METHOD_CK45 = 1, METHOD_RKF45 = 2, METHOD_GBS = 3 };
 
 template <int M>
 struct Pair;
@@ -600,34 +600,140 @@ __device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>
     e.pth = h * weighted(P::e, kpth);
 }
 
+// Gragg-Bulirsch-Stoer extrapolation (Sec. 3.2).  A macro-step h is covered
+// kGbsColumns times by Gragg's modified midpoint rule, row i (0-based) with
+// n_i = 2(i+1) substeps and the final smoothing step; Richardson extrapolation
+// in (h/n)^2 (Aitken-Neville) turns row i's midpoint result into
+//   T[i][k+1] = T[i][k] + (T[i][k] - T[i-1][k]) / ((n_i / n_{i-k-1})^2 - 1).
+// T[K-1][K-1] propagates; T[K-1][K-1] - T[K-1][K-2] is the error estimate, of
+// order 2K - 2, so the controller's exponent is -1/(2K - 1).
+constexpr int kGbsColumns = 6;
+
+struct GbsWeights {
+    double w[kGbsColumns][kGbsColumns - 1];   // 1 / ((n_i / n_{i-k-1})^2 - 1), zero for k >= i
+};
+
+constexpr GbsWeights make_gbs_weights()
+{
+    GbsWeights g{};
+    for (int i = 0; i < kGbsColumns; ++i)
+        for (int k = 0; k < kGbsColumns - 1; ++k) {
+            if (k < i) {
+                const double ratio = (double)(2 * (i + 1)) / (double)(2 * (i - k));
+                g.w[i][k] = 1.0 / (ratio * ratio - 1.0);
+            } else {
+                g.w[i][k] = 0.0;
+            }
+        }
+    return g;
+}
+
+__constant__ GbsWeights kGbsW = make_gbs_weights();
+
+// One macro-step of the extrapolation with FP64 stages: the same outputs as
+// stages64 (y5 = T[K-1][K-1], k7 = f(y5), H(y5), cos(theta5), error vector).
+// The row and substep loops are uniform across the wavefront (every lane runs
+// the same substep counts), so one inlined right-hand side serves all 42
+// substep evaluations.  Rows are folded into the tableau in place, all
+// kGbsColumns entries per row: entries past the row's own take a zero weight
+// and copy their left neighbour, so register indices stay compile-time.
+template <int KIND>
+__device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
+                                             Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
+{
+    constexpr int K = kGbsColumns;
+    const double a = R.a;
+    double Tt[K], Tr[K], Tth[K], Tph[K], Tpr[K], Tpth[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Tt[k] = Tr[k] = Tth[k] = Tph[k] = Tpr[k] = Tpth[k] = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < K; ++i) {
+        const int n = 2 * (i + 1);
+        const double hs = h / (double)n;
+        const double h2 = 2.0 * hs;
+        // z_0 = y, z_1 = y + hs f(y)
+        double pt_ = R.t, pr_ = R.r, pth_ = R.th, pph_ = R.ph, ppr_ = R.pr, ppth_ = R.pth;
+        double zt = fma(hs, R.k.t, R.t), zr = fma(hs, R.k.r, R.r), zth = fma(hs, R.k.th, R.th);
+        double zph = fma(hs, R.k.ph, R.ph), zpr = fma(hs, R.k.pr, R.pr), zpth = fma(hs, R.k.pth, R.pth);
+        Deriv<double> dz;
+        for (int m = 1;; ++m) {
+            double Hd, cd;
+            M.rhs(a, zr, zth, zpr, zpth, R.pt, R.pph, dz, Hd, cd);
+            if (m == n) break;
+            // z_{m+1} = z_{m-1} + 2 hs f(z_m)
+            const double nt = fma(h2, dz.t, pt_), nr = fma(h2, dz.r, pr_), nth = fma(h2, dz.th, pth_);
+            const double nph = fma(h2, dz.ph, pph_), npr = fma(h2, dz.pr, ppr_), npth = fma(h2, dz.pth, ppth_);
+            pt_ = zt; pr_ = zr; pth_ = zth; pph_ = zph; ppr_ = zpr; ppth_ = zpth;
+            zt = nt; zr = nr; zth = nth; zph = nph; zpr = npr; zpth = npth;
+        }
+        // smoothing: (z_n + z_{n-1} + hs f(z_n)) / 2
+        double vt = 0.5 * (pt_ + fma(hs, dz.t, zt)), vr = 0.5 * (pr_ + fma(hs, dz.r, zr));
+        double vth = 0.5 * (pth_ + fma(hs, dz.th, zth)), vph = 0.5 * (pph_ + fma(hs, dz.ph, zph));
+        double vpr = 0.5 * (ppr_ + fma(hs, dz.pr, zpr)), vpth = 0.5 * (ppth_ + fma(hs, dz.pth, zpth));
+        // fold into the tableau
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) {
+            const double w = kGbsW.w[i][k];
+            const double ut = fma(vt - Tt[k], w, vt), ur = fma(vr - Tr[k], w, vr);
+            const double uth = fma(vth - Tth[k], w, vth), uph = fma(vph - Tph[k], w, vph);
+            const double upr = fma(vpr - Tpr[k], w, vpr), upth = fma(vpth - Tpth[k], w, vpth);
+            Tt[k] = vt; Tr[k] = vr; Tth[k] = vth; Tph[k] = vph; Tpr[k] = vpr; Tpth[k] = vpth;
+            vt = ut; vr = ur; vth = uth; vph = uph; vpr = upr; vpth = upth;
+        }
+        Tt[K - 1] = vt; Tr[K - 1] = vr; Tth[K - 1] = vth; Tph[K - 1] = vph; Tpr[K - 1] = vpr; Tpth[K - 1] = vpth;
+    }
+    y5.t = Tt[K - 1];
+    y5.r = Tr[K - 1];
+    y5.th = Tth[K - 1];
+    y5.ph = Tph[K - 1];
+    y5.pr = Tpr[K - 1];
+    y5.pth = Tpth[K - 1];
+    e.t = Tt[K - 1] - Tt[K - 2];
+    e.r = Tr[K - 1] - Tr[K - 2];
+    e.th = Tth[K - 1] - Tth[K - 2];
+    e.ph = Tph[K - 1] - Tph[K - 2];
+    e.pr = Tpr[K - 1] - Tpr[K - 2];
+    e.pth = Tpth[K - 1] - Tpth[K - 2];
+    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+}
+
 __device__ __forceinline__ double sq_ratio(double e, double y0, double y1, double atol, double rtol)
 {
     const double z = e * rcp64(fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
     return z * z;
 }
 
-// x^(-1/5) for 1e-6 <= x <= 1e5: an FP32 estimate refined by two Newton steps
-// on y^-5 = x (y <- y (6 - x y^5) / 5), which take the ~1e-7 relative error of
-// the estimate below an ulp of the double result.
-__device__ __forceinline__ double pow_m_one_fifth(double x)
+// x^(-1/P) for P = 5 or 11 on the range step_factor passes in: an FP32
+// estimate refined by two Newton steps on y^-P = x
+// (y <- y ((P + 1) - x y^P) / P), which take the ~1e-7 relative error of the
+// estimate below an ulp of the double result.
+template <int P>
+__device__ __forceinline__ double pow_m_inv(double x)
 {
-    double y = (double)exp2f(-0.2f * log2f((float)x));
+    static_assert(P == 5 || P == 11, "exponent");
+    double y = (double)exp2f(log2f((float)x) * (-1.0f / (float)P));
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const double y2 = y * y;
-        const double y5 = y2 * y2 * y;
-        y = y * fma(-x, y5, 6.0) * 0.2;
+        const double y4 = y2 * y2;
+        const double yp = P == 5 ? y4 * y : y4 * y4 * y2 * y;
+        y = y * fma(-x, yp, (double)(P + 1)) * (1.0 / (double)P);
     }
     return y;
 }
 
-// Step-size factor of the elementary controller: min(fmx, max(0.2, 0.9 err^-1/5)).
-// Outside [1e-6, 1e5] the clamps decide the result without the power.
+// Step-size factor of the elementary controller:
+// min(fmx, max(0.2, 0.9 err^(-1/P))), P = 5 for the 5(4) pairs and 2K - 1 for
+// the extrapolation.  Below lo and above hi the clamps decide the result
+// without the power (0.9 lo^(-1/P) >= 10 and 0.9 hi^(-1/P) <= 0.2).
+template <int P>
 __device__ __forceinline__ double step_factor(double err, double fmx)
 {
-    if (err < 1e-6) return fmx;
-    if (err > 1e5) return 0.2;
-    return fmin(fmx, fmax(0.2, 0.9 * pow_m_one_fifth(err)));
+    constexpr double lo = P == 5 ? 1e-6 : 1e-12;
+    constexpr double hi = P == 5 ? 1e5 : 1e8;
+    if (err < lo) return fmx;
+    if (err > hi) return 0.2;
+    return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<P>(err)));
 }
 
 // One attempt; returns true when the ray has terminated (outputs written).
@@ -654,6 +760,8 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
         }
         if constexpr (METHOD == METHOD_DP45)
             stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
+        else if constexpr (METHOD == METHOD_GBS)
+            stages64_gbs<KIND>(R, M, h, y5, k7, e, H5, c5);
         else
             stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
     }
@@ -670,7 +778,8 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     // elementary controller, evaluated once for both outcomes: after a
     // rejection (or for one) the step may not grow
     const bool ok = err <= 1.0;
-    const double fac = isnan(err) ? 0.2 : step_factor(err, (ok && !R.rej_prev) ? 10.0 : 1.0);
+    constexpr int P = METHOD == METHOD_GBS ? 2 * kGbsColumns - 1 : 5;
+    const double fac = isnan(err) ? 0.2 : step_factor<P>(err, (ok && !R.rej_prev) ? 10.0 : 1.0);
     if (!ok) {
         // rejected; a NaN or infinite error also lands here
         R.n_rej++;
@@ -1114,6 +1223,7 @@ static const void* trace_kernel_for(int kind, int prec, int method)
     if (kind == 0 && prec == 0 && method == 1) return (const void*)trace_persistent<0, 0, 1>;
     if (kind == 0 && prec == 0 && method == 2) return (const void*)trace_persistent<0, 0, 2>;
     if (kind == 0 && prec == 1 && method == 0) return (const void*)trace_persistent<0, 1, 0>;
+    if (kind == 0 && prec == 0 && method == 3) return (const void*)trace_persistent<0, 0, 3>;
     if (kind == 1 && prec == 0 && method == 0) return (const void*)trace_persistent<1, 0, 0>;
     return nullptr;
 }

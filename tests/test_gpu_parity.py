@@ -177,6 +177,100 @@ def test_six_stage_pairs_full_images(T, orc, method):
     assert not np.array_equal(d["n_accept"], g["n_accept"])
 
 
+# ------------------------------------------------- Gragg-Bulirsch-Stoer
+# The extrapolation's error estimate T[K][K] - T[K][K-1] is a difference of two
+# states of size |y|; far from the hole the truncation error is below the
+# rounding of that difference, so the controller's step factor carries
+# rounding noise and the step sequence of two correct FP64 implementations
+# diverges (shown on the CPU: the oracle and its FMA-contracted build disagree
+# on the step count of ~half the rays).  Outputs then differ by the method's
+# own accuracy (events are read off the cubic interpolant of macro-steps
+# hundreds of M long).  Hence two bars: one macro-step, fixed by the arithmetic
+# alone, to 1e-12; whole images within a small multiple of the oracle's own
+# rounding spread.
+GBS_NEAR_CAM = dict(r_obs=8.0, theta_obs=math.pi / 3, nx=24, ny=24, alpha_min=-5.0, alpha_max=5.0,
+                    beta_min=-5.0, beta_max=5.0)
+SPREAD_FACTOR = 5.0
+
+
+def assert_within_spread(g, o, f, band, label):
+    rg, rf = compare(g, o, band, 0.0), compare(f, o, band, 0.0)
+    say(label, "gpu-oracle", {k: (rg[k]["p50"], rg[k]["max"]) for k in ("hit_r", "hit_g", "final_theta", "final_phi")})
+    say(label, "fma-oracle", {k: (rf[k]["p50"], rf[k]["max"]) for k in ("hit_r", "hit_g", "final_theta", "final_phi")})
+    assert rg["class_mismatch_off_band"] <= rf["class_mismatch_off_band"] + 2, (rg, rf)
+    for k in ("hit_r", "hit_g", "final_theta", "final_phi", "flux"):
+        assert rg[k]["p50"] <= SPREAD_FACTOR * rf[k]["p50"] + 1e-12, (k, rg[k], rf[k])
+        assert rg[k]["max"] <= 2 * SPREAD_FACTOR * rf[k]["max"] + 1e-9, (k, rg[k], rf[k])
+    same_go = np.mean(g["n_accept"] == o["n_accept"])
+    same_fo = np.mean(f["n_accept"] == o["n_accept"])
+    assert same_go >= 0.5 * same_fo, (same_go, same_fo)
+
+
+@pytest.mark.parametrize("h0_frac", [0.02, 0.1, 0.3, 1.0])
+def test_extrapolation_first_macro_step(T, orc, h0_frac):
+    """One macro-step (max_steps = 1) from a camera in the strong field (r = 8)
+    and from the far camera: accept/reject and the state after it agree to
+    1e-12 (the largest first step is rejected: the state stays put)."""
+    disk = dict(r_in=0.0, r_out=20.0, max_hits=3)
+    for cam in (GBS_NEAR_CAM, dict(W.WORKLOADS["kerr09_512"]["cameras"][0], nx=24, ny=24)):
+        sv = dict(rtol=1e-8, atol=1e-10, h0_frac=h0_frac, horizon_factor=1.01, r_escape=1.1 * cam["r_obs"],
+                  event_tol=1e-12, max_steps=1, method=3)
+        say("case gbs one macro-step h0_frac", h0_frac, "r_obs", cam["r_obs"])
+        g = gpu_trace(T, 0.9, cam, disk, sv)
+        o = oracle_trace(orc, 0.9, cam, disk, sv)
+        assert np.array_equal(g["n_accept"], o["n_accept"]) and np.array_equal(g["n_reject"], o["n_reject"])
+        assert np.array_equal(g["cls"], o["cls"])
+        d = np.abs(g["final_rtp"] - o["final_rtp"]) / np.maximum(1.0, np.abs(o["final_rtp"]))
+        assert d.max() < 1e-12, d.max()
+        # |H| after one step is at the rounding level of H itself (~1e-15)
+        assert np.allclose(g["h_drift"], o["h_drift"], rtol=1e-6, atol=1e-14)
+
+
+def test_extrapolation_full_images_within_rounding_spread(T, orc):
+    """Gragg-Bulirsch-Stoer (Sec. 3.2) on the Schwarzschild shadow and a ragged
+    Kerr image with the disk: the GPU's distance to the oracle is bounded by
+    the oracle's distance to its own FMA-contracted build."""
+    for name, nx, ny in (("schwarzschild_64", None, None), ("kerr09_512", 37, 29)):
+        w = W.WORKLOADS[name]
+        cam = dict(w["cameras"][0]) if nx is None else dict(w["cameras"][0], nx=nx, ny=ny)
+        sv = dict(w["solver"], method=3)
+        say("case gbs", name, cam["nx"], cam["ny"])
+        g = gpu_trace(T, w["a"], cam, w["disk"], sv)
+        o = oracle_trace(orc, w["a"], cam, w["disk"], sv)
+        m = orc.make_metric(w["a"])
+        f = orc.trace(m, [orc.make_camera(cam)], orc.make_disk(w["disk"]), orc.make_solver(sv), fma=True)
+        band = edge_band(class_key(o).reshape(cam["ny"], cam["nx"])).ravel()
+        assert_within_spread(g, o, f, band, name)
+        # macro-steps: far fewer attempts per ray than the 5(4) pair needs
+        d = gpu_trace(T, w["a"], cam, w["disk"], w["solver"])
+        assert (g["n_accept"] + g["n_reject"]).mean() < 0.5 * (d["n_accept"] + d["n_reject"]).mean()
+
+
+def test_extrapolation_kerr09_512_sampled(T, orc):
+    """The 512^2 Kerr image with the disk at the gate tolerance, sampled."""
+    w = W.WORKLOADS["kerr09_512"]
+    cam = w["cameras"][0]
+    sv = dict(w["solver"], rtol=3e-10, atol=3e-12, method=3)
+    say("case kerr09_512 gbs sampled")
+    g = gpu_trace(T, w["a"], cam, w["disk"], sv)
+    nx, ny, nsample = cam["nx"], cam["ny"], 200
+    rng = np.random.default_rng(5)
+    ii, jj = rng.integers(1, nx - 1, nsample), rng.integers(1, ny - 1, nsample)
+    ids = np.array([(j + dj) * nx + (i + di) for i, j in zip(ii, jj) for dj in (-1, 0, 1) for di in (-1, 0, 1)])
+    uniq, inv = np.unique(ids, return_inverse=True)
+    m = orc.make_metric(w["a"])
+    args = (m, [orc.make_camera(cam)], orc.make_disk(w["disk"]), orc.make_solver(sv))
+    o_u, f_u = orc.trace(*args, ray_ids=uniq), orc.trace(*args, ray_ids=uniq, fma=True)
+    key9 = class_key(o_u)[inv].reshape(nsample, 9)
+    band = np.any(key9 != key9[:, 4:5], axis=1)
+    centre = inv.reshape(nsample, 9)[:, 4]
+    o = {k: v[centre] for k, v in o_u.items()}
+    f = {k: v[centre] for k, v in f_u.items()}
+    gs = {k: v[uniq[centre]] for k, v in g.items()}
+    assert_within_spread(gs, o, f, band, "kerr09_512 sampled")
+    assert np.all(g["cls"] != 2)
+
+
 def test_single_pixel_and_single_row(T, orc):
     w = W.WORKLOADS["kerr09_512"]
     for nx, ny in ((1, 1), (17, 1), (1, 5)):
