@@ -109,6 +109,8 @@ def _declare(L):
     L.or_rk_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
     L.or_gbs_fixed.argtypes = [C.c_int, C.c_int, USER_RHS, dp, C.c_double, C.c_int, dp]
     L.or_gbs_columns.restype = C.c_int
+    L.or_verlet_fixed.argtypes = [C.c_int, USER_RHS, dp, C.c_double, C.c_int]
+    L.or_verlet_fixed.restype = C.c_int
     L.or_hermite.argtypes = [C.c_double] * 6
     L.or_hermite.restype = C.c_double
     L.or_bisect_count.argtypes = [C.c_double, C.c_double]
@@ -234,7 +236,7 @@ def bisect_count(h, tol): return lib().or_bisect_count(h, tol)
 def max_threads(): return lib().or_max_threads()
 
 
-METHODS = {"dp45": 0, "ck45": 1, "rkf45": 2, "gbs": 3}
+METHODS = {"dp45": 0, "ck45": 1, "rkf45": 2, "gbs": 3, "verlet": 4}
 RK_METHODS = {"dp45": 0, "ck45": 1, "rkf45": 2}
 
 
@@ -271,6 +273,17 @@ def rk_fixed(method: int, f, y0, h: float, nsteps: int):
     e = np.zeros(n)
     lib().or_rk_fixed(method, n, cfun, _dptr(y), h, nsteps, _dptr(e))
     return y, e
+
+
+def verlet_fixed(f, y0, h: float, nsteps: int):
+    """nsteps fixed Verlet steps on a Hamiltonian system y = [x, p] with
+    f(y) = [dH/dp, -dH/dx]; returns (y, steps completed)."""
+    n = len(y0)
+    assert n % 2 == 0 and n <= 16
+    cfun = _user_rhs(f)
+    y = np.ascontiguousarray(y0, dtype=np.float64).copy()
+    done = lib().or_verlet_fixed(n, cfun, _dptr(y), h, nsteps)
+    return y, done
 
 
 def gbs_columns() -> int:

@@ -17,6 +17,7 @@
  *   - Sec. 3.2: Dormand-Prince, Cash-Karp and Fehlberg 5(4) pairs with local
  *     extrapolation and embedded error estimate; Gragg-Bulirsch-Stoer
  *     modified-midpoint extrapolation with error-controlled macro-steps;
+ *     a fixed-step symmetric (generalized Stormer-)Verlet scheme;
  *     horizon / escape / equatorial-disk events
  *     refined by bisection on the step's cubic Hermite interpolant to about
  *     1e-12 in the affine parameter.
@@ -26,7 +27,8 @@
  * written out where it is used): the tetrad's e_(t)^phi component, the pixel
  * grid, the sign flip used for backward tracing, the step-size controller,
  * the failure limits, the event rules and the bisection count, the
- * extrapolation's substep sequence, column count and error estimate, the emitter's
+ * extrapolation's substep sequence, column count and error estimate, the
+ * Verlet scheme for a non-separable Hamiltonian and its step, the emitter's
  * Keplerian angular velocity, the a = 0 guard in the flux sum.
  *
  * The metric derivatives come from hyper-dual arithmetic (exact first and
@@ -568,6 +570,91 @@ void or_gbs_fixed(int K, int n, or_user_rhs f, double* y, double h, int nsteps, 
 }
 
 /* ------------------------------------------------------------------ */
+/* Verlet (Sec. 3.2): fixed step, time-reversible, symmetric.  H(x, p) = */
+/* 1/2 g^{ab}(x) p_a p_b does not split into a kinetic and a potential   */
+/* part, so the scheme is the symmetric generalization of Stormer-Verlet */
+/* to such Hamiltonians: an implicit half step in the momenta, a         */
+/* trapezoidal step in the positions, an explicit closing half step:     */
+/*   p' = p - (h/2) dH/dx(x, p')                                         */
+/*   x+ = x + (h/2) [dH/dp(x, p') + dH/dp(x+, p')]                       */
+/*   p+ = p' - (h/2) dH/dx(x+, p')                                       */
+/* (for H = T(p) + V(x) this is the classical velocity Verlet step).     */
+/* The map is symplectic and symmetric, so H stays bounded.  The two     */
+/* implicit stages are solved by fixed-point iteration from an explicit  */
+/* predictor, to a relative change of VERLET_ITER_TOL; a stage that does */
+/* not converge has (for this step) no solution near the current one,    */
+/* which happens close to the horizon, where dH/dx grows like 1/Delta.   */
+/* The state is [x (n/2 components), p (n/2 components)] and f returns   */
+/* [dH/dp, -dH/dx].                                                      */
+/* ------------------------------------------------------------------ */
+#define VERLET_MAX_ITER 50
+#define VERLET_ITER_TOL 1e-14
+
+/* One step from y (fy = f(y)); returns 0 when an implicit stage does not
+ * converge within VERLET_MAX_ITER iterations. */
+static int verlet_step(int n, rhs_fn f, void* ctx, const double* y, const double* fy, double h, double* ynew)
+{
+    int d = n / 2;
+    double z[16] = {0.0}, fz[16], ph[8], v0[8], xk[8];
+    /* stage 1: p' = p + (h/2) [-dH/dx](x, p'), predictor p + (h/2) [-dH/dx](x, p) */
+    for (int i = 0; i < d; ++i) ph[i] = y[d + i] + 0.5 * h * fy[d + i];
+    int conv = 0;
+    for (int it = 0; it < VERLET_MAX_ITER && !conv; ++it) {
+        for (int i = 0; i < d; ++i) { z[i] = y[i]; z[d + i] = ph[i]; }
+        f(ctx, z, fz);
+        double dmax = 0.0, vmax = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double pn = y[d + i] + 0.5 * h * fz[d + i];
+            dmax = fmax(dmax, fabs(pn - ph[i]));
+            vmax = fmax(vmax, fabs(pn));
+            ph[i] = pn;
+        }
+        conv = dmax <= VERLET_ITER_TOL * fmax(1.0, vmax);
+    }
+    if (!conv) return 0;
+    /* stage 2: x+ = x + (h/2) [dH/dp(x, p') + dH/dp(x+, p')], predictor x + h dH/dp(x, p') */
+    for (int i = 0; i < d; ++i) { z[i] = y[i]; z[d + i] = ph[i]; }
+    f(ctx, z, fz);
+    for (int i = 0; i < d; ++i) { v0[i] = fz[i]; xk[i] = y[i] + h * v0[i]; }
+    conv = 0;
+    for (int it = 0; it < VERLET_MAX_ITER && !conv; ++it) {
+        for (int i = 0; i < d; ++i) { z[i] = xk[i]; z[d + i] = ph[i]; }
+        f(ctx, z, fz);
+        double dmax = 0.0, vmax = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double xn = y[i] + 0.5 * h * (v0[i] + fz[i]);
+            dmax = fmax(dmax, fabs(xn - xk[i]));
+            vmax = fmax(vmax, fabs(xn));
+            xk[i] = xn;
+        }
+        conv = dmax <= VERLET_ITER_TOL * fmax(1.0, vmax);
+    }
+    if (!conv) return 0;
+    /* stage 3: p+ = p' + (h/2) [-dH/dx](x+, p') */
+    for (int i = 0; i < d; ++i) { z[i] = xk[i]; z[d + i] = ph[i]; }
+    f(ctx, z, fz);
+    for (int i = 0; i < d; ++i) {
+        ynew[i] = xk[i];
+        ynew[d + i] = ph[i] + 0.5 * h * fz[d + i];
+    }
+    return 1;
+}
+
+/* Test hook: nsteps fixed Verlet steps on a Hamiltonian system y = [x, p]
+ * (n even, <= 16); returns the number of steps completed. */
+int or_verlet_fixed(int n, or_user_rhs f, double* y, double h, int nsteps)
+{
+    struct user_ctx u = {f, n};
+    double fy[16], yn[16];
+    for (int s = 0; s < nsteps; ++s) {
+        f(y, fy, n);
+        if (!verlet_step(n, user_tramp, &u, y, fy, h, yn)) return s;
+        for (int d = 0; d < n; ++d) y[d] = yn[d];
+    }
+    return nsteps;
+}
+
+/* ------------------------------------------------------------------ */
 /* Dense output and event location (Sec. 3.2).                          */
 /* ------------------------------------------------------------------ */
 
@@ -687,18 +774,26 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
 
     for (;;) {
         if ((int64_t)out->n_accept + out->n_reject >= sv->max_steps) break;
-        if (sv->method == OR_METHOD_GBS)
-            gbs_attempt(OR_GBS_COLUMNS, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
-        else
-            rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
-        /* RMS error norm over all eight components */
-        double acc = 0.0;
-        for (int d = 0; d < NSTATE; ++d) {
-            double sc = sv->atol + sv->rtol * fmax(fabs(y[d]), fabs(y5[d]));
-            double z = e[d] / sc;
-            acc += z * z;
+        double err;
+        if (sv->method == OR_METHOD_VERLET) {
+            /* fixed step, no error control: every converged step is taken */
+            if (!verlet_step(NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5)) break;
+            rhs_m(m, y5, k7);
+            err = 0.0;
+        } else {
+            if (sv->method == OR_METHOD_GBS)
+                gbs_attempt(OR_GBS_COLUMNS, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
+            else
+                rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
+            /* RMS error norm over all eight components */
+            double acc = 0.0;
+            for (int d = 0; d < NSTATE; ++d) {
+                double sc = sv->atol + sv->rtol * fmax(fabs(y[d]), fabs(y5[d]));
+                double z = e[d] / sc;
+                acc += z * z;
+            }
+            err = sqrt(acc / (double)NSTATE);
         }
-        double err = sqrt(acc / (double)NSTATE);
         if (!(err <= 1.0)) {
             /* rejected (a NaN or infinite error also lands here) */
             out->n_reject++;
@@ -789,6 +884,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
          * on the step right after a rejection */
         double fmax_ = rejected_prev ? 1.0 : 10.0;
         double fac = err == 0.0 ? fmax_ : fmin(fmax_, fmax(0.2, 0.9 * pow(err, expo)));
+        if (sv->method == OR_METHOD_VERLET) fac = 1.0;
         lambda += h;
         for (int d = 0; d < NSTATE; ++d) { y[d] = y5[d]; k1[d] = k7[d]; }
         h *= fac;

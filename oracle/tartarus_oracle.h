@@ -39,8 +39,10 @@ typedef struct {
 } or_disk;
 
 /* method: 0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg 5(4) pair, 3 Gragg-
- * Bulirsch-Stoer extrapolation with OR_GBS_COLUMNS columns (Sec. 3.2). */
+ * Bulirsch-Stoer extrapolation with OR_GBS_COLUMNS columns, 4 Verlet with the
+ * fixed step h0_frac * r_obs (Sec. 3.2). */
 #define OR_METHOD_GBS 3
+#define OR_METHOD_VERLET 4
 #define OR_GBS_COLUMNS 6
 typedef struct {
     double rtol, atol, h0_frac, horizon_factor, r_escape, event_tol;

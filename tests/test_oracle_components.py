@@ -220,6 +220,57 @@ def test_gbs_columns_used_for_rays(orc):
     assert orc.gbs_columns() == 6
 
 
+# ------------------------------------------------------------------ Verlet
+def test_verlet_harmonic_oscillator_closed_form(orc):
+    """On H = (p^2 + q^2)/2 the step is the linear map M = [[1 - h^2/2, h],
+    [-h (1 - h^2/4), 1 - h^2/2]] (det 1, trace 2 - h^2), so N steps are
+    M^N = U_{N-1}(c) M - U_{N-2}(c) I with c = cos(theta) = 1 - h^2/2 and the
+    Chebyshev U_k = sin((k+1) theta) / sin(theta)."""
+    h, N = 0.1, 1000
+    y0 = np.array([1.0, 0.3])
+    y, done = orc.verlet_fixed(lambda y: np.array([y[1], -y[0]]), y0, h, N)
+    assert done == N
+    th = math.acos(1 - h * h / 2)
+    M = np.array([[1 - h * h / 2, h], [-h * (1 - h * h / 4), 1 - h * h / 2]])
+    U = lambda k: math.sin((k + 1) * th) / math.sin(th)
+    assert np.abs(y - (U(N - 1) * M - U(N - 2) * np.eye(2)) @ y0).max() < 1e-12
+
+
+def nonseparable(y):
+    """H = p^2 (1 + x^2) / 2 + x^2 / 2: kinetic and potential parts do not split."""
+    return np.array([y[1] * (1 + y[0] ** 2), -(y[0] * y[1] ** 2 + y[0])])
+
+
+def test_verlet_time_reversible_and_symplectic(orc):
+    y0 = np.array([0.7, 0.4])
+    yf, _ = orc.verlet_fixed(nonseparable, y0, 0.05, 2000)
+    yb, done = orc.verlet_fixed(nonseparable, yf, -0.05, 2000)
+    assert done == 2000
+    assert np.abs(yb - y0).max() < 1e-11          # h -> -h retraces the path
+    d, J = 1e-6, np.zeros((2, 2))
+    for k in range(2):
+        e = np.zeros(2)
+        e[k] = d
+        J[:, k] = (orc.verlet_fixed(nonseparable, y0 + e, 0.2, 1)[0]
+                   - orc.verlet_fixed(nonseparable, y0 - e, 0.2, 1)[0]) / (2 * d)
+    assert abs(np.linalg.det(J) - 1.0) < 1e-8    # area preserving (one degree of freedom)
+
+
+def test_verlet_second_order_and_bounded_energy(orc):
+    from scipy.integrate import solve_ivp
+    y0, T = np.array([0.7, 0.4]), 3.0
+    ref = solve_ivp(lambda t, y: nonseparable(y), (0, T), y0, method="DOP853", rtol=1e-13, atol=1e-14).y[:, -1]
+    errs = [np.abs(orc.verlet_fixed(nonseparable, y0, T / n, n)[0] - ref).max() for n in (60, 120, 240)]
+    assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2
+    H = lambda y: 0.5 * y[1] ** 2 * (1 + y[0] ** 2) + 0.5 * y[0] ** 2
+    y, dev = y0.copy(), []
+    for _ in range(1000):
+        y, _ = orc.verlet_fixed(nonseparable, y, 0.1, 50)
+        dev.append(abs(H(y) - H(y0)))
+    dev = np.array(dev)
+    assert dev[-100:].max() < 1.05 * dev[:100].max()   # no secular drift over 5e4 steps
+
+
 # ----------------------------------------------------------------- events
 def test_hermite_exact_on_cubics(orc):
     rng = np.random.default_rng(3)

@@ -208,6 +208,55 @@ def test_schwarzschild_deflection_at_accepted_states(orc, alpha, method):
         assert st[k, 2] == pytest.approx(math.pi / 2, abs=1e-12)
 
 
+@pytest.mark.parametrize("alpha", [9.0, 15.0])
+def test_verlet_deflection_converges_second_order(orc, alpha):
+    """Verlet with a fixed step h: the total deflection approaches the orbit
+    quadrature as h^2, and so does the constraint residual."""
+    leg = deflection_leg(alpha)
+    expect = leg(1 / D) + leg(1 / 1100.0)
+    errs, hs = [], []
+    for h in (1.0, 0.5, 0.25):
+        o = single_ray(orc, 0.0, 90.0, alpha, 0.0, solver=W.solver(method=4, h0_frac=h / D))
+        assert o["cls"][0] == orc.ESCAPED and o["n_reject"][0] == 0
+        assert o["final_rtp"][0, 0] == pytest.approx(1100.0, abs=1e-9)
+        errs.append(abs(abs(o["final_rtp"][0, 2]) - expect))
+        hs.append(o["h_drift"][0])
+    assert 3.7 < errs[0] / errs[1] < 4.3 and 3.7 < errs[1] / errs[2] < 4.3
+    assert 3.7 < hs[0] / hs[1] < 4.3 and 3.7 < hs[1] / hs[2] < 4.3
+
+
+def test_verlet_capture_matches_exact_criterion(orc):
+    """Fixed step h = 0.01 from r = 100 with the stop at 1.05 r_+: every ray
+    ends ESCAPED or CAPTURED as the exact criterion says.  Closer to the
+    horizon dH/dx grows like 1/Delta and the implicit momentum stage has no
+    solution near the current one for this step; such rays end FAILED."""
+    r_obs, n, a = 100.0, 12, 0.9
+    c = W.camera(r_obs, 60.0, n, n, 8.0)
+    m = orc.make_metric(a)
+    sv = W.solver(method=4, h0_frac=0.01 / r_obs, r_escape=1.1 * r_obs, horizon_factor=1.05)
+    o = orc.trace(m, orc.make_camera(c), orc.make_disk(None), orc.make_solver(sv))
+    cls = o["cls"].reshape(n, n)
+    assert not np.any(cls == orc.FAILED)
+    assert np.all(o["n_reject"] == 0)
+    rp = orc.horizon(a)
+    ca = orc.make_camera(c)
+    exact = np.zeros_like(cls)
+    for j in range(n):
+        for i in range(n):
+            q = orc.initial_state(m, ca, i, j)
+            E, L, Q = conserved(q, a, c["theta_obs"])
+            exact[j, i] = 1 if captured_exact(a, L / E, Q / E ** 2, r_obs, rp) else 0
+    band = edge_band(exact)
+    assert np.array_equal(cls[~band], exact[~band])
+    assert 0 < exact.sum() < n * n
+    # the stop at 1.01 r_+ is out of reach for some captured rays at this step
+    sv = W.solver(method=4, h0_frac=0.01 / r_obs, r_escape=1.1 * r_obs, horizon_factor=1.01)
+    o = orc.trace(m, orc.make_camera(c), orc.make_disk(None), orc.make_solver(sv))
+    failed = o["cls"] == orc.FAILED
+    assert failed.any() and np.all(exact.ravel()[failed & ~band.ravel()] == 1)
+    assert np.all(o["final_rtp"][failed, 0] < 1.1 * rp)
+
+
 def paper_ray(orc, b, r0, solver, disk=None):
     """A Schwarzschild ray launched from r0 = D in the equatorial plane with impact parameter b."""
     c = dict(r_obs=r0, theta_obs=math.pi / 2, nx=1, ny=1, alpha_min=b * math.sqrt(1 - 2 / r0),
