@@ -603,13 +603,16 @@ static int verlet_step(int n, rhs_fn f, void* ctx, const double* y, const double
         for (int i = 0; i < d; ++i) { z[i] = y[i]; z[d + i] = ph[i]; }
         f(ctx, z, fz);
         double dmax = 0.0, vmax = 0.0;
+        int finite = 1;
         for (int i = 0; i < d; ++i) {
             double pn = y[d + i] + 0.5 * h * fz[d + i];
+            finite = finite && isfinite(pn);
             dmax = fmax(dmax, fabs(pn - ph[i]));
             vmax = fmax(vmax, fabs(pn));
             ph[i] = pn;
         }
-        conv = dmax <= VERLET_ITER_TOL * fmax(1.0, vmax);
+        /* (fmax ignores a NaN operand, so a non-finite iterate is excluded explicitly) */
+        conv = finite && dmax <= VERLET_ITER_TOL * fmax(1.0, vmax);
     }
     if (!conv) return 0;
     /* stage 2: x+ = x + (h/2) [dH/dp(x, p') + dH/dp(x+, p')], predictor x + h dH/dp(x, p') */
@@ -621,13 +624,15 @@ static int verlet_step(int n, rhs_fn f, void* ctx, const double* y, const double
         for (int i = 0; i < d; ++i) { z[i] = xk[i]; z[d + i] = ph[i]; }
         f(ctx, z, fz);
         double dmax = 0.0, vmax = 0.0;
+        int finite = 1;
         for (int i = 0; i < d; ++i) {
             double xn = y[i] + 0.5 * h * (v0[i] + fz[i]);
+            finite = finite && isfinite(xn);
             dmax = fmax(dmax, fabs(xn - xk[i]));
             vmax = fmax(vmax, fabs(xn));
             xk[i] = xn;
         }
-        conv = dmax <= VERLET_ITER_TOL * fmax(1.0, vmax);
+        conv = finite && dmax <= VERLET_ITER_TOL * fmax(1.0, vmax);
     }
     if (!conv) return 0;
     /* stage 3: p+ = p' + (h/2) [-dH/dx](x+, p') */
