@@ -340,6 +340,21 @@ def main():
                            "attempts_per_ray": float(attl.mean()),
                            "h_gate_max": float(ol["h_gate"][ol["cls"] != 2].max()),
                            "failed_rays": int((ol["cls"] == 2).sum())}
+        # fixed-step Verlet (Sec. 3.2): h = 0.01 on a 256^2 image of the same scene,
+        # stop at 1.05 r_+ (where its implicit stages still converge), two launches
+        wv = dict(cam, nx=256, ny=256)
+        nv = wv["nx"] * wv["ny"]
+        sv = dict(w["solver"], method=T.METHOD_VERLET, h0_frac=0.01 / wv["r_obs"], horizon_factor=1.05)
+        la = (metric, [T.make_camera(wv)], disk, T.make_solver(sv, T.PREC_FP64))
+        outv = T.alloc_outputs(nv)
+        log("bench: leg verlet_h0.01_256")
+        wl, km = time_leg(T, torch, la, outv, 2, 1)
+        ol = T.to_numpy(outv)
+        legs["verlet_h0.01_256"] = {"rays": nv, "rays_per_s": nv * 2 / wl, "kernel_ms": km,
+                                    "steps_per_ray": float(ol["n_accept"].mean()),
+                                    "steps_per_s": float(ol["n_accept"].sum()) * 2 / wl,
+                                    "h_gate_max": float(ol["h_gate"][ol["cls"] != 2].max()),
+                                    "failed_rays": int((ol["cls"] == 2).sum())}
         legs.update(workload_legs(T, torch, W, {}))
         legs["mixed_over_fp64_same_rtol"] = legs["mixed_rtol1e-8"]["rays_per_s"] / legs["fp64_rtol1e-8"]["rays_per_s"]
         legs["mixed_rtol1e-8_over_fp64_gate"] = legs["mixed_rtol1e-8"]["rays_per_s"] / value

@@ -121,15 +121,26 @@ typedef struct {
  * Gragg-Bulirsch-Stoer extrapolation: per macro-step six modified-midpoint
  * sweeps with 2, 4, ..., 12 substeps, Richardson extrapolation in h^2 to order
  * 12, the difference to the order-10 entry as error estimate (42 right-hand
- * sides per attempt, against 6 for a pair).  For every method, h0_frac,
- * max_steps and the error norm keep their meaning (an attempt is one
- * macro-step), and events are located on the cubic Hermite interpolant of the
- * accepted step.  Mixed precision and the tabulated metric need DP45. */
+ * sides per attempt, against 6 for a pair); or TARTARUS_METHOD_VERLET, the
+ * symmetric, symplectic generalized Stormer-Verlet scheme with the FIXED step
+ * h0_frac * r_obs and no error control (rtol and atol are not used; every
+ * step counts as accepted).  Its two implicit stages are solved by fixed-point
+ * iteration; a ray whose stage does not converge (close to the horizon, where
+ * dH/dx grows like 1/Delta, a fixed step eventually has no nearby solution)
+ * ends FAILED at its current state.  Fixed steps resolve the strong field
+ * only if they are small (~0.01 M near the hole), so Verlet traces take
+ * 1e5-1e6 steps per ray from a distant camera; with horizon_factor >= 1.05
+ * the captured rays of a spin-0.9 hole reach the stop radius at h <= 0.01.
+ * For every method, h0_frac and max_steps keep their meaning (an attempt is
+ * one macro-step or one fixed step), and events are located on the cubic
+ * Hermite interpolant of the accepted step.  Mixed precision and the
+ * tabulated metric need DP45. */
 enum {
     TARTARUS_METHOD_DP45 = 0,
     TARTARUS_METHOD_CK45 = 1,
     TARTARUS_METHOD_RKF45 = 2,
-    TARTARUS_METHOD_GBS = 3
+    TARTARUS_METHOD_GBS = 3,
+    TARTARUS_METHOD_VERLET = 4
 };
 typedef struct {
     double rtol, atol, h0_frac, horizon_factor, r_escape, event_tol;

@@ -185,9 +185,9 @@ int check_solver(const tartarus_solver* s)
     if (s->max_steps < 1) return fail(TARTARUS_E_INVALID, "max_steps must be >= 1");
     if (s->precision != TARTARUS_PREC_FP64 && s->precision != TARTARUS_PREC_MIXED)
         return fail(TARTARUS_E_INVALID, "unknown precision");
-    if (s->method < TARTARUS_METHOD_DP45 || s->method > TARTARUS_METHOD_GBS)
+    if (s->method < TARTARUS_METHOD_DP45 || s->method > TARTARUS_METHOD_VERLET)
         return fail(TARTARUS_E_INVALID,
-                    "unknown method (0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg, 3 Gragg-Bulirsch-Stoer)");
+                    "unknown method (0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg, 3 Gragg-Bulirsch-Stoer, 4 Verlet)");
     if (s->precision == TARTARUS_PREC_MIXED && s->method != TARTARUS_METHOD_DP45)
         return fail(TARTARUS_E_INVALID, "mixed precision is provided with Dormand-Prince 5(4) only");
     return TARTARUS_OK;
@@ -298,7 +298,7 @@ void fill_args(LaunchArgs& A, const tartarus_metric* m, const tartarus_solver* s
     }
 }
 
-int tune_key(int kind, int prec, int method) { return (kind * 2 + prec) * 4 + method; }
+int tune_key(int kind, int prec, int method) { return (kind * 2 + prec) * 8 + method; }
 
 tartarus_launch default_launch(int kind, int prec, int method)
 {

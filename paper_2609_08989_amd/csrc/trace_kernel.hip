@@ -50,7 +50,7 @@ constexpr double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0, 
 // stage matrix a, fifth-order weights b (propagated) and error weights
 // e = b - b* (b* the embedded fourth-order weights).  f(y5) closes each step
 // as the next step's first stage and the event interpolant's end slope.
-enum { METHOD_DP45 = 0, METHOD_CK45 = 1, METHOD_RKF45 = 2, METHOD_GBS = 3 };
+enum { METHOD_DP45 = 0, METHOD_CK45 = 1, METHOD_RKF45 = 2, METHOD_GBS = 3, METHOD_VERLET = 4 };
 
 template <int M>
 struct Pair;
@@ -697,6 +697,75 @@ __device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>
     M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
 }
 
+// Verlet (Sec. 3.2): a fixed step of the generalized Stormer-Verlet scheme for
+// the non-separable H(x, p) = 1/2 g^{ab}(x) p_a p_b, symmetric and symplectic:
+//   p' = p - (h/2) dH/dx(x, p')                      (implicit in p')
+//   x+ = x + (h/2) [dH/dp(x, p') + dH/dp(x+, p')]    (implicit in x+)
+//   p+ = p' - (h/2) dH/dx(x+, p')
+// Both implicit stages iterate to a fixed point from an explicit predictor,
+// stopping once the largest change of a component is at most 1e-14 of
+// max(1, largest component).  p_t and p_phi never change (dH/dt = dH/dphi = 0)
+// but enter the size of the momenta.  Returns false when a stage has not
+// converged after kVerletMaxIter iterations (near the horizon, where dH/dx
+// grows like 1/Delta, the stage has no solution close to the current state
+// for a fixed step).  Lanes iterate independently; the loops end for every
+// lane after at most kVerletMaxIter passes.
+constexpr int kVerletMaxIter = 50;
+constexpr double kVerletTol = 1e-14;
+
+template <int KIND>
+__device__ __forceinline__ bool stages_verlet(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
+                                              Deriv<double>& k7, double& H5, double& c5)
+{
+    const double a = R.a, hh = 0.5 * h;
+    Deriv<double> d;
+    double Hd, cd;
+    // stage 1
+    double pr = fma(hh, R.k.pr, R.pr), pth = fma(hh, R.k.pth, R.pth);
+    const double pconst = fmax(fabs(R.pt), fabs(R.pph));
+    bool conv = false;
+    for (int it = 0; it < kVerletMaxIter && !conv; ++it) {
+        M.rhs(a, R.r, R.th, pr, pth, R.pt, R.pph, d, Hd, cd);
+        const double npr = fma(hh, d.pr, R.pr), npth = fma(hh, d.pth, R.pth);
+        const double dmax = fmax(fabs(npr - pr), fabs(npth - pth));
+        const double vmax = fmax(fmax(fabs(npr), fabs(npth)), pconst);
+        pr = npr;
+        pth = npth;
+        // fmax drops a NaN operand: a non-finite iterate never counts as converged
+        conv = isfinite(npr) && isfinite(npth) && dmax <= kVerletTol * fmax(1.0, vmax);
+    }
+    if (!conv) return false;
+    // stage 2
+    M.rhs(a, R.r, R.th, pr, pth, R.pt, R.pph, d, Hd, cd);
+    const double v0t = d.t, v0r = d.r, v0th = d.th, v0ph = d.ph;
+    double xt = fma(h, v0t, R.t), xr = fma(h, v0r, R.r), xth = fma(h, v0th, R.th), xph = fma(h, v0ph, R.ph);
+    conv = false;
+    for (int it = 0; it < kVerletMaxIter && !conv; ++it) {
+        M.rhs(a, xr, xth, pr, pth, R.pt, R.pph, d, Hd, cd);
+        const double nt = fma(hh, v0t + d.t, R.t), nr = fma(hh, v0r + d.r, R.r);
+        const double nth = fma(hh, v0th + d.th, R.th), nph = fma(hh, v0ph + d.ph, R.ph);
+        const double dmax = fmax(fmax(fabs(nt - xt), fabs(nr - xr)), fmax(fabs(nth - xth), fabs(nph - xph)));
+        const double vmax = fmax(fmax(fabs(nt), fabs(nr)), fmax(fabs(nth), fabs(nph)));
+        xt = nt;
+        xr = nr;
+        xth = nth;
+        xph = nph;
+        conv = isfinite(nt) && isfinite(nr) && isfinite(nth) && isfinite(nph) &&
+               dmax <= kVerletTol * fmax(1.0, vmax);
+    }
+    if (!conv) return false;
+    // stage 3
+    M.rhs(a, xr, xth, pr, pth, R.pt, R.pph, d, Hd, cd);
+    y5.t = xt;
+    y5.r = xr;
+    y5.th = xth;
+    y5.ph = xph;
+    y5.pr = fma(hh, d.pr, pr);
+    y5.pth = fma(hh, d.pth, pth);
+    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+    return true;
+}
+
 __device__ __forceinline__ double sq_ratio(double e, double y0, double y1, double atol, double rtol)
 {
     const double z = e * rcp64(fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
@@ -748,48 +817,57 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     Deriv<double> y5, k7, e;
     double H5, c5;
     bool used32 = false;
-    if (PREC == 1 && KIND == 0 && far_field(R, A)) {
-        stages32(R, h, y5, k7, e, H5, c5);
-        used32 = true;
-    } else {
-        if (PREC == 1 && R.k32) {
-            // leaving the FP32 regime: re-evaluate the first stage in FP64
-            double Hd;
-            M.rhs(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth);
-            R.k32 = 0;
-        }
-        if constexpr (METHOD == METHOD_DP45)
-            stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
-        else if constexpr (METHOD == METHOD_GBS)
-            stages64_gbs<KIND>(R, M, h, y5, k7, e, H5, c5);
-        else
-            stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
-    }
-    R.n_f32 += used32 ? 1 : 0;
-    const double atol = A.atol, rtol = A.rtol;
-    double acc = sq_ratio(e.t, R.t, y5.t, atol, rtol);
-    acc += sq_ratio(e.r, R.r, y5.r, atol, rtol);
-    acc += sq_ratio(e.th, R.th, y5.th, atol, rtol);
-    acc += sq_ratio(e.ph, R.ph, y5.ph, atol, rtol);
-    acc += sq_ratio(e.pr, R.pr, y5.pr, atol, rtol);
-    acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
-    // p_t and p_phi have zero error (their derivatives vanish identically)
-    const double err = sqrt(acc * 0.125);
-    // elementary controller, evaluated once for both outcomes: after a
-    // rejection (or for one) the step may not grow
-    const bool ok = err <= 1.0;
-    constexpr int P = METHOD == METHOD_GBS ? 2 * kGbsColumns - 1 : 5;
-    const double fac = isnan(err) ? 0.2 : step_factor<P>(err, (ok && !R.rej_prev) ? 10.0 : 1.0);
-    if (!ok) {
-        // rejected; a NaN or infinite error also lands here
-        R.n_rej++;
-        R.h = h * fac;
-        R.rej_prev = 1;
-        if (R.h < 1e-14 * fmax(1.0, fabs(R.lam))) {
+    double fac = 1.0;
+    if constexpr (METHOD == METHOD_VERLET) {
+        // fixed step, no error control: a converged step is always taken
+        if (!stages_verlet<KIND>(R, M, h, y5, k7, H5, c5)) {
             ray_fail(R, A);
             return true;
         }
-        return false;
+    } else {
+        if (PREC == 1 && KIND == 0 && far_field(R, A)) {
+            stages32(R, h, y5, k7, e, H5, c5);
+            used32 = true;
+        } else {
+            if (PREC == 1 && R.k32) {
+                // leaving the FP32 regime: re-evaluate the first stage in FP64
+                double Hd;
+                M.rhs(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth);
+                R.k32 = 0;
+            }
+            if constexpr (METHOD == METHOD_DP45)
+                stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
+            else if constexpr (METHOD == METHOD_GBS)
+                stages64_gbs<KIND>(R, M, h, y5, k7, e, H5, c5);
+            else
+                stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
+        }
+        R.n_f32 += used32 ? 1 : 0;
+        const double atol = A.atol, rtol = A.rtol;
+        double acc = sq_ratio(e.t, R.t, y5.t, atol, rtol);
+        acc += sq_ratio(e.r, R.r, y5.r, atol, rtol);
+        acc += sq_ratio(e.th, R.th, y5.th, atol, rtol);
+        acc += sq_ratio(e.ph, R.ph, y5.ph, atol, rtol);
+        acc += sq_ratio(e.pr, R.pr, y5.pr, atol, rtol);
+        acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
+        // p_t and p_phi have zero error (their derivatives vanish identically)
+        const double err = sqrt(acc * 0.125);
+        // elementary controller, evaluated once for both outcomes: after a
+        // rejection (or for one) the step may not grow
+        const bool ok = err <= 1.0;
+        constexpr int P = METHOD == METHOD_GBS ? 2 * kGbsColumns - 1 : 5;
+        fac = isnan(err) ? 0.2 : step_factor<P>(err, (ok && !R.rej_prev) ? 10.0 : 1.0);
+        if (!ok) {
+            // rejected; a NaN or infinite error also lands here
+            R.n_rej++;
+            R.h = h * fac;
+            R.rej_prev = 1;
+            if (R.h < 1e-14 * fmax(1.0, fabs(R.lam))) {
+                ray_fail(R, A);
+                return true;
+            }
+            return false;
+        }
     }
     R.n_acc++;
     if (!(isfinite(y5.t) && isfinite(y5.r) && isfinite(y5.th) && isfinite(y5.ph) && isfinite(y5.pr) &&
@@ -1224,6 +1302,7 @@ static const void* trace_kernel_for(int kind, int prec, int method)
     if (kind == 0 && prec == 0 && method == 2) return (const void*)trace_persistent<0, 0, 2>;
     if (kind == 0 && prec == 1 && method == 0) return (const void*)trace_persistent<0, 1, 0>;
     if (kind == 0 && prec == 0 && method == 3) return (const void*)trace_persistent<0, 0, 3>;
+    if (kind == 0 && prec == 0 && method == 4) return (const void*)trace_persistent<0, 0, 4>;
     if (kind == 1 && prec == 0 && method == 0) return (const void*)trace_persistent<1, 0, 0>;
     return nullptr;
 }

@@ -21,7 +21,7 @@ ESCAPED, CAPTURED, FAILED = 0, 1, 2
 METRIC_KERR, METRIC_TABLE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 ORDER_DEFAULT, ORDER_PIXEL, ORDER_COST = 0, 1, 2
-METHOD_DP45, METHOD_CK45, METHOD_RKF45, METHOD_GBS = 0, 1, 2, 3
+METHOD_DP45, METHOD_CK45, METHOD_RKF45, METHOD_GBS, METHOD_VERLET = 0, 1, 2, 3, 4
 
 
 class TartarusError(RuntimeError):

@@ -61,10 +61,11 @@ def test_validate_accepts_the_workloads(T):
     (lambda m, c, d, s: setattr(s, "horizon_factor", 0.9), "horizon_factor"),
     (lambda m, c, d, s: setattr(s, "max_steps", 0), "max_steps"),
     (lambda m, c, d, s: setattr(s, "precision", 5), "precision"),
-    (lambda m, c, d, s: setattr(s, "method", 4), "method"),
+    (lambda m, c, d, s: setattr(s, "method", 5), "method"),
     (lambda m, c, d, s: setattr(s, "method", -1), "method"),
     (lambda m, c, d, s: (setattr(s, "method", 1), setattr(s, "precision", 1)), "mixed needs DP45"),
     (lambda m, c, d, s: (setattr(s, "method", 3), setattr(s, "precision", 1)), "mixed needs DP45"),
+    (lambda m, c, d, s: (setattr(s, "method", 4), setattr(s, "precision", 1)), "mixed needs DP45"),
     (lambda m, c, d, s: setattr(d, "max_hits", 4), "max_hits"),
     (lambda m, c, d, s: setattr(m, "kind", 7), "kind"),
 ])
@@ -82,7 +83,7 @@ def test_table_metric_rules(T):
     m.table = C.c_void_p(0x1000)
     m.nr, m.nth, m.r_min, m.r_max = 512, 256, 1.9, 2000.0
     assert T.tartarus_validate(m, c, d, s) == T.OK
-    for method in (T.METHOD_CK45, T.METHOD_GBS):
+    for method in (T.METHOD_CK45, T.METHOD_GBS, T.METHOD_VERLET):
         s.method = method
         assert T.tartarus_validate(m, c, d, s) == T.E_INVALID  # tabulated metric: DP45 only
     s.method = T.METHOD_DP45
@@ -95,7 +96,7 @@ def test_table_metric_rules(T):
 
 def test_six_stage_pairs_and_extrapolation_are_accepted(T):
     m, c, d, s = good()
-    for method in (T.METHOD_CK45, T.METHOD_RKF45, T.METHOD_GBS):
+    for method in (T.METHOD_CK45, T.METHOD_RKF45, T.METHOD_GBS, T.METHOD_VERLET):
         s.method = method
         assert T.tartarus_validate(m, c, d, s) == T.OK
 

@@ -271,6 +271,41 @@ def test_extrapolation_kerr09_512_sampled(T, orc):
     assert np.all(g["cls"] != 2)
 
 
+# ------------------------------------------------------------------ Verlet
+VERLET_CAM = dict(r_obs=100.0, theta_obs=math.pi / 3, nx=24, ny=24, alpha_min=-12.0, alpha_max=12.0,
+                  beta_min=-12.0, beta_max=12.0)
+
+
+def verlet_solver(h, horizon_factor):
+    return dict(rtol=1e-8, atol=1e-10, h0_frac=h / VERLET_CAM["r_obs"], horizon_factor=horizon_factor,
+                r_escape=1.1 * VERLET_CAM["r_obs"], event_tol=1e-12, max_steps=1000000, method=4)
+
+
+def test_verlet_image_with_disk(T, orc):
+    """Fixed-step Verlet (Sec. 3.2), h = 0.01, ~2e4 steps per ray, spin 0.9
+    with the disk: no error control means no step decisions to disagree on,
+    and the FP64 bar holds (the oracle's plain and FMA builds agree to 1e-12)."""
+    disk = dict(r_in=0.0, r_out=20.0, max_hits=3)
+    say("case verlet 24x24 h=0.01 stop 1.05 r+")
+    g, o = full_image_parity(T, orc, 0.9, VERLET_CAM, disk, verlet_solver(0.01, 1.05))
+    assert np.all(g["n_reject"] == 0) and np.array_equal(g["n_accept"], o["n_accept"])
+    assert np.all(g["cls"] != 2) and (g["n_hits"] > 0).sum() > 100
+
+
+def test_verlet_stage_without_solution_fails_the_ray(T, orc):
+    """With the stop at 1.01 r_+ some captured rays reach radii where the
+    implicit momentum stage has no solution near the current state for this
+    step: they end FAILED on both sides, at the same state."""
+    say("case verlet 24x24 h=0.01 stop 1.01 r+")
+    sv = verlet_solver(0.01, 1.01)
+    g = gpu_trace(T, 0.9, VERLET_CAM, None, sv)
+    o = oracle_trace(orc, 0.9, VERLET_CAM, None, sv)
+    assert (o["cls"] == 2).any()
+    assert np.array_equal(g["cls"], o["cls"]) and np.array_equal(g["n_accept"], o["n_accept"])
+    f = o["cls"] == 2
+    assert np.abs(g["final_rtp"][f] / o["final_rtp"][f] - 1).max() < FP64_TOL
+
+
 def test_single_pixel_and_single_row(T, orc):
     w = W.WORKLOADS["kerr09_512"]
     for nx, ny in ((1, 1), (17, 1), (1, 5)):
