@@ -20,7 +20,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # the same arithmetic, used to measure how far rounding alone moves a result.
 _LIB_FMA = os.path.join(_HERE, "liboracle_fma.so")
 
-ESCAPED, CAPTURED, FAILED = 0, 1, 2
+ESCAPED, CAPTURED, FAILED, ON_DISK = 0, 1, 2, 3
 
 
 def build(force: bool = True, fma: bool = False) -> str:
@@ -47,7 +47,8 @@ class Camera(C.Structure):
 
 
 class Disk(C.Structure):
-    _fields_ = [("r_in", C.c_double), ("r_out", C.c_double), ("max_hits", C.c_int)]
+    _fields_ = [("r_in", C.c_double), ("r_out", C.c_double), ("max_hits", C.c_int), ("opaque", C.c_int),
+                ("shading", C.c_int)]
 
 
 class Solver(C.Structure):
@@ -147,8 +148,8 @@ def make_camera(c: dict) -> Camera:
 
 def make_disk(d: dict | None) -> Disk:
     if d is None:
-        return Disk(0.0, 0.0, 0)
-    return Disk(d.get("r_in", 0.0), d["r_out"], d.get("max_hits", 3))
+        return Disk(0.0, 0.0, 0, 0, 0)
+    return Disk(d.get("r_in", 0.0), d["r_out"], d.get("max_hits", 3), d.get("opaque", 0), d.get("shading", 0))
 
 
 def make_solver(s: dict) -> Solver:

@@ -754,6 +754,8 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
     double r_gate = 1.5 * rp;
     int max_hits = disk ? disk->max_hits : 0;
     if (max_hits > OR_MAX_HITS) max_hits = OR_MAX_HITS;
+    int opaque = disk && disk->opaque && max_hits > 0;
+    int intrinsic = disk && disk->shading == OR_SHADE_INTRINSIC;
     double r_in = 0.0, r_out = 0.0;
     if (max_hits > 0) {
         r_in = disk->r_in > 0.0 ? disk->r_in : or_isco(a);
@@ -854,10 +856,17 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
                     double g2 = g * g;
                     out->hit_r[k] = rr;
                     out->hit_g[k] = g;
-                    out->hit_flux[k] = g2 * g2 * F;            /* Eq. (16) */
+                    /* Eq. (16); the intrinsic map drops the shift (Fig. KerrUHD b) */
+                    out->hit_flux[k] = intrinsic ? F : g2 * g2 * F;
                     out->hit_lambda[k] = lambda + s * h;
                     out->hit_order[k] = out->n_cross;
                     out->intensity += out->hit_flux[k];
+                    if (opaque) {
+                        /* optically thick disk (Sec. 2.3): the ray ends on it */
+                        terminal = EV_DISK;
+                        term_s = s;
+                        break;
+                    }
                 }
             } else {
                 terminal = ev_kind[p];
@@ -877,7 +886,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
             ++nrec;
         }
         if (terminal >= 0) {
-            out->cls = terminal == EV_HORIZON ? OR_CAPTURED : OR_ESCAPED;
+            out->cls = terminal == EV_HORIZON ? OR_CAPTURED : terminal == EV_ESCAPE ? OR_ESCAPED : OR_ON_DISK;
             out->final_rtp[0] = interp(&st, R_, term_s);
             out->final_rtp[1] = interp(&st, TH_, term_s);
             out->final_rtp[2] = interp(&st, PH_, term_s);

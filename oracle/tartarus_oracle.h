@@ -16,6 +16,7 @@
 #define OR_ESCAPED 0
 #define OR_CAPTURED 1
 #define OR_FAILED 2
+#define OR_ON_DISK 3       /* ended on an opaque disk */
 #define OR_MAX_HITS 3
 
 typedef struct {
@@ -32,10 +33,15 @@ typedef struct {
     double alpha_min, alpha_max, beta_min, beta_max;
 } or_camera;
 
+#define OR_SHADE_OBSERVED 0   /* hit flux g^4 F (Eq. (16))                          */
+#define OR_SHADE_INTRINSIC 1  /* hit flux F: redshift and beaming off (Fig. KerrUHD b) */
+
 typedef struct {
     double r_in;           /* <= 0 means r_ISCO                                      */
     double r_out;
     int max_hits;          /* 0..3; 0 = no disk                                      */
+    int opaque;            /* 1: the first crossing on the disk ends the ray         */
+    int shading;           /* OR_SHADE_OBSERVED or OR_SHADE_INTRINSIC                */
 } or_disk;
 
 /* method: 0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg 5(4) pair, 3 Gragg-

@@ -411,6 +411,57 @@ def poly_table(nr, nth, r_min, r_max):
     return tab, f
 
 
+def test_intrinsic_map_is_mirror_symmetric_without_spin(orc):
+    """Fig. KerrUHD (b): with the shift switched off the disk map shows the
+    intrinsic emission F(r_em) and, for a = 0, is left-right symmetric (the
+    scene is symmetric under phi -> -phi, i.e. alpha -> -alpha); the observed
+    map g^4 F is not (the approaching side is beamed)."""
+    n, c = 32, W.camera(D, 80.0, 32, 32, 18.0)
+    base = dict(r_in=0.0, r_out=15.0, max_hits=3)
+    m = orc.make_metric(0.0)
+    obs = orc.trace(m, orc.make_camera(c), orc.make_disk(base), orc.make_solver(W.solver()))
+    ins = orc.trace(m, orc.make_camera(c), orc.make_disk(dict(base, shading=1)), orc.make_solver(W.solver()))
+    hit = obs["n_hits"] > 0
+    assert hit.sum() > 100
+    assert np.array_equal(obs["hit_r"], ins["hit_r"]) and np.array_equal(obs["hit_g"], ins["hit_g"])
+    for k in range(3):
+        mk = obs["n_hits"] > k
+        F = np.array([orc.nt_flux(0.0, orc.isco(0.0), 15.0, r) for r in obs["hit_r"][mk, k]])
+        assert np.allclose(ins["hit_flux"][mk, k], F, rtol=1e-15, atol=0)
+        assert np.allclose(obs["hit_flux"][mk, k], obs["hit_g"][mk, k] ** 4 * F, rtol=1e-14, atol=0)
+    I_in, I_ob = ins["intensity"].reshape(n, n), obs["intensity"].reshape(n, n)
+    scale = I_in.max()
+    assert np.abs(I_in - I_in[:, ::-1]).max() < 1e-9 * scale
+    assert np.abs(I_ob - I_ob[:, ::-1]).max() > 0.1 * I_ob.max()
+
+
+def test_opaque_disk_ends_rays_at_the_first_hit(orc):
+    """Sec. 2.3's optically thick disk: a ray ends at its first crossing that
+    lies on the disk (class ON_DISK), at that crossing's point on the equator;
+    rays without a crossing on the disk are traced as before."""
+    a, n = 0.9, 28
+    c = W.camera(D, 75.0, n, n, 20.0)
+    base = dict(r_in=0.0, r_out=20.0, max_hits=3)
+    m = orc.make_metric(a)
+    tr = orc.trace(m, orc.make_camera(c), orc.make_disk(base), orc.make_solver(W.solver()))
+    op = orc.trace(m, orc.make_camera(c), orc.make_disk(dict(base, opaque=1)), orc.make_solver(W.solver()))
+    hit = tr["n_hits"] > 0
+    assert 100 < hit.sum() < n * n
+    assert np.array_equal(op["cls"] == orc.ON_DISK, hit)
+    assert np.all(op["n_hits"][hit] == 1) and np.all(op["n_hits"][~hit] == 0)
+    for f in ("hit_r", "hit_g", "hit_flux", "hit_lambda", "hit_order"):
+        assert np.array_equal(op[f][hit, 0], tr[f][hit, 0]), f
+    assert np.array_equal(op["intensity"][hit], op["hit_flux"][hit, 0])
+    assert np.array_equal(op["final_rtp"][hit, 0], tr["hit_r"][hit, 0])
+    assert np.abs(np.cos(op["final_rtp"][hit, 1])).max() < 1e-11          # on the equator
+    r_in = orc.isco(a)
+    assert np.all((op["final_rtp"][hit, 0] >= r_in) & (op["final_rtp"][hit, 0] <= 20.0))
+    for f in ("cls", "final_rtp", "n_accept", "n_cross"):
+        assert np.array_equal(op[f][~hit], tr[f][~hit]), f
+    # the opaque ray stops: fewer steps than the transparent one
+    assert np.all(op["n_accept"][hit] <= tr["n_accept"][hit])
+
+
 def test_table_interpolation_exact_on_bicubics(orc):
     nr, nth, r_min, r_max = 17, 9, 2.0, 500.0
     tab, f = poly_table(nr, nth, r_min, r_max)
