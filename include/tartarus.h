@@ -67,6 +67,7 @@ typedef enum {
 #define TARTARUS_ESCAPED 0
 #define TARTARUS_CAPTURED 1
 #define TARTARUS_FAILED 2
+#define TARTARUS_ON_DISK 3   /* ended on an opaque disk (tartarus_disk.opaque) */
 
 #define TARTARUS_METRIC_KERR 0
 #define TARTARUS_METRIC_TABLE 1
@@ -102,11 +103,22 @@ typedef struct {
 } tartarus_camera;
 
 /* Thin Novikov-Thorne disk in theta = pi/2 (Sec. 2.3).  r_in <= 0 selects the
- * prograde ISCO.  max_hits in 0..3; 0 disables the disk event. */
+ * prograde ISCO.  max_hits in 0..3; 0 disables the disk event.
+ * opaque = 0: crossings do not stop the ray; the first max_hits crossings on
+ *   the disk are recorded and later ones counted.  opaque = 1 (optically
+ *   thick, Sec. 2.3; needs max_hits >= 1): the first crossing on the disk ends
+ *   the ray there, cls = TARTARUS_ON_DISK, final_rtp = the crossing point.
+ * shading = TARTARUS_SHADE_OBSERVED: hit_flux = g^4 F(r_em) (Eq. (16));
+ *   TARTARUS_SHADE_INTRINSIC: hit_flux = F(r_em), the map with the redshift
+ *   and beaming switched off (Fig. KerrUHD b); hit_g is reported either way. */
+#define TARTARUS_SHADE_OBSERVED 0
+#define TARTARUS_SHADE_INTRINSIC 1
 typedef struct {
     double r_in;
     double r_out;
     int max_hits;
+    int opaque;
+    int shading;
 } tartarus_disk;
 
 /* Integrator settings (Sec. 3.2).  rtol > 0, atol > 0, h0_frac > 0,
@@ -221,9 +233,9 @@ int tartarus_trace_launch(const tartarus_metric* metric, const tartarus_camera* 
                           const tartarus_outputs* out, const tartarus_launch* launch, void* hip_stream);
 
 /* Time candidate launch shapes on the given trace (synchronously, on
- * hip_stream), keep the fastest for this (metric kind, precision) for the rest
- * of the process, and write it to *best.  The outputs hold the last run's
- * results. */
+ * hip_stream; each candidate is the best of three runs), keep the fastest for
+ * this (metric kind, precision, method) for the rest of the process, and write
+ * it to *best.  The outputs hold the last run's results. */
 int tartarus_autotune(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
                       const tartarus_disk* disk, const tartarus_solver* solver,
                       const tartarus_outputs* out, void* hip_stream, tartarus_launch* best);

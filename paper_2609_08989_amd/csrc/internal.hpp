@@ -13,7 +13,7 @@ struct DevJob {
     long long ray_count;
     int nx, ny;
     int max_hits;
-    int pad0;
+    int disk_flags;                 // DISK_OPAQUE | DISK_INTRINSIC
     double a;
     double r_obs, theta_obs;
     double alpha_min, alpha_max, beta_min, beta_max;
@@ -47,8 +47,11 @@ struct DevJob {
 // Terminal step at REC_TERM: r, th, phi as (y0, dy0/dlam, y1, dy1/dlam) each,
 // then h, lam, target radius, cos(th0); for rays that end without a terminal
 // root (failed) only the three y0 are meaningful.  REC_CODE: terminal kind
-// (0 none, 1 horizon, 2 escape) + 4 if the equator was crossed in that step.
+// (0 none, 1 horizon, 2 escape) + 4 if the equator was crossed in that step,
+// or 8: the step's equatorial crossing is on an opaque disk and ends the ray.
 // REC_INTS: int32 cls, n_hits, n_accept, n_reject, n_fp32, n_cross, order[3].
+constexpr int DISK_OPAQUE = 1;     // the first crossing on the disk ends the ray
+constexpr int DISK_INTRINSIC = 2;  // hit flux F instead of g^4 F
 constexpr int REC_SLOT_LEN = 11;
 constexpr int REC_TERM = 33;
 constexpr int REC_CODE = 49;

@@ -197,6 +197,10 @@ int check_disk(const tartarus_disk* d)
 {
     if (!d) return fail(TARTARUS_E_INVALID, "disk is NULL");
     if (d->max_hits < 0 || d->max_hits > 3) return fail(TARTARUS_E_INVALID, "max_hits must be in 0..3");
+    if (d->opaque != 0 && d->opaque != 1) return fail(TARTARUS_E_INVALID, "disk opaque must be 0 or 1");
+    if (d->opaque && d->max_hits < 1) return fail(TARTARUS_E_INVALID, "an opaque disk needs max_hits >= 1");
+    if (d->shading != TARTARUS_SHADE_OBSERVED && d->shading != TARTARUS_SHADE_INTRINSIC)
+        return fail(TARTARUS_E_INVALID, "unknown disk shading");
     if (d->max_hits > 0) {
         if (!std::isfinite(d->r_in) || !std::isfinite(d->r_out)) return fail(TARTARUS_E_INVALID, "non-finite disk radii");
         if (!(d->r_out > 0.0)) return fail(TARTARUS_E_INVALID, "disk r_out must be > 0");
@@ -240,6 +244,7 @@ void fill_job(DevJob& J, const tartarus_metric* m, const tartarus_camera& c, con
     J.nx = c.nx;
     J.ny = c.ny;
     J.max_hits = d->max_hits;
+    J.disk_flags = (d->opaque ? DISK_OPAQUE : 0) | (d->shading == TARTARUS_SHADE_INTRINSIC ? DISK_INTRINSIC : 0);
     J.a = m->a;
     J.r_obs = c.r_obs;
     J.theta_obs = c.theta_obs;
@@ -488,6 +493,10 @@ extern "C" int tartarus_build_kerr_table(double a, int nr, int nth, double r_min
 // ---------------------------------------------------------------------------
 namespace {
 
+// Best of kTuneRepeats traces with launch shape L: a single run varies by a
+// few percent from launch to launch, enough to mislead a coordinate search.
+constexpr int kTuneRepeats = 3;
+
 int time_trace(const tartarus_metric* metric, const tartarus_camera* cams, int ncams, const tartarus_disk* disk,
                const tartarus_solver* solver, const tartarus_outputs* out, const tartarus_launch& L,
                hipStream_t stream, float& ms)
@@ -495,16 +504,21 @@ int time_trace(const tartarus_metric* metric, const tartarus_camera* cams, int n
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, stream));
-    int rc = enqueue_trace(metric, cams, ncams, disk, solver, out, &L, stream);
-    if (rc) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return rc;
+    ms = 0.f;
+    for (int rep = 0; rep < kTuneRepeats; ++rep) {
+        HIP_TRY(hipEventRecord(e0, stream));
+        int rc = enqueue_trace(metric, cams, ncams, disk, solver, out, &L, stream);
+        if (rc) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+        HIP_TRY(hipEventRecord(e1, stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        if (rep == 0 || t < ms) ms = t;
     }
-    HIP_TRY(hipEventRecord(e1, stream));
-    HIP_TRY(hipEventSynchronize(e1));
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return TARTARUS_OK;
@@ -529,6 +543,12 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
     tartarus_launch cur = default_launch(kind, prec, method);
     int grid = 0;
     if ((rc = resolve_launch(kind, prec, method, &cur, cur, grid))) return rc;
+    if (cur.order == TARTARUS_ORDER_DEFAULT) {
+        // report the order the default stands for on this trace
+        long long n = 0;
+        for (int c = 0; c < ncams; ++c) n += (long long)cams[c].nx * cams[c].ny;
+        cur.order = n >= kCostOrderMin ? TARTARUS_ORDER_COST : TARTARUS_ORDER_PIXEL;
+    }
     float best_ms = 0.f;
     if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;  // warm-up
     if ((rc = time_trace(metric, cams, ncams, disk, solver, out, cur, stream, best_ms))) return rc;

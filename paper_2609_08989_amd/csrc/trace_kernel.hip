@@ -100,7 +100,7 @@ __device__ __forceinline__ double weighted(const double (&w)[N], const double (&
     return acc;
 }
 
-enum { CLS_ESCAPED = 0, CLS_CAPTURED = 1, CLS_FAILED = 2 };
+enum { CLS_ESCAPED = 0, CLS_CAPTURED = 1, CLS_FAILED = 2, CLS_ON_DISK = 3 };
 
 struct Ray {
     double t, r, th, ph, pr, pth, pt, pph;
@@ -112,6 +112,7 @@ struct Ray {
     float guard_r, guard_th;  // mixed precision: FP32 only while |p_r| >= guard_r and |p_theta| >= guard_th
     int n_acc, n_rej, n_f32, n_cross, n_hits, rej_prev, max_hits, job;
     int k32;           // R.k was evaluated in FP32 (mixed precision)
+    int opaque;        // the first crossing on the disk ends the ray
     long long local;
     double* rec;       // this ray's record for the finishing pass
     double r_in, r_out;  // disk radii
@@ -341,6 +342,7 @@ __device__ bool ray_init(Ray& R, long long gid, const LaunchArgs& A, const JobDi
     R.h = A.h0_frac * J.r_obs;
     R.n_acc = R.n_rej = R.n_f32 = R.n_cross = R.n_hits = R.rej_prev = 0;
     R.max_hits = J.max_hits;
+    R.opaque = J.disk_flags & DISK_OPAQUE;
     R.job = jb;
     R.local = pix;
     R.rec = J.rec + pix * REC_DOUBLES;
@@ -384,6 +386,51 @@ __device__ __forceinline__ double equator_root(const Cubic& pth, double th0, dou
 {
     const bool wide = !(th0 > -M_PI_2 && th0 < 1.5 * M_PI && th1 > -M_PI_2 && th1 < 1.5 * M_PI);
     return wide ? locate_equator_wide(pth, cth0 > 0.0, h, tol) : locate_root(pth, M_PI_2, cth0 < 0.0, h, tol);
+}
+
+// The step that ends a ray, for the finishing pass to locate its root on:
+// r, theta, phi as (y0, dy0/dlam, y1, dy1/dlam), h, lam, the target radius of
+// a radial event, cos(theta0).
+__device__ __forceinline__ void terminal_step(const Ray& R, double h, const Deriv<double>& y5,
+                                              const Deriv<double>& k7, double target)
+{
+    double* t = R.rec + REC_TERM;
+    t[0] = R.r;
+    t[1] = R.k.r;
+    t[2] = y5.r;
+    t[3] = k7.r;
+    t[4] = R.th;
+    t[5] = R.k.th;
+    t[6] = y5.th;
+    t[7] = k7.th;
+    t[8] = R.ph;
+    t[9] = R.k.ph;
+    t[10] = y5.ph;
+    t[11] = k7.ph;
+    t[12] = h;
+    t[13] = R.lam;
+    t[14] = target;
+    t[15] = R.cth;
+}
+
+// An equatorial crossing of an opaque disk's ray (Sec. 2.3, optically thick):
+// it counts, and returns whether it lies on the disk, which ends the ray.  The
+// step's radial Bernstein hull decides without a root unless it straddles an
+// edge of the disk; the finishing pass locates the crossing either way (same
+// cubic, same root finder).
+__device__ __forceinline__ bool opaque_hit(Ray& R, double h, const Deriv<double>& y5, const Deriv<double>& k7,
+                                           double tol)
+{
+    R.n_cross++;
+    const double b1 = fma(h * (1.0 / 3.0), R.k.r, R.r), b2 = fma(-h * (1.0 / 3.0), k7.r, y5.r);
+    const double lo = fmin(fmin(R.r, y5.r), fmin(b1, b2)), hi = fmax(fmax(R.r, y5.r), fmax(b1, b2));
+    constexpr double m = 1e-12;
+    if (hi < R.r_in * (1.0 - m) || lo > R.r_out * (1.0 + m)) return false;
+    if (lo >= R.r_in * (1.0 + m) && hi <= R.r_out * (1.0 - m)) return true;
+    const Cubic pth(R.th, R.k.th, y5.th, k7.th, h);
+    const double sd = equator_root(pth, R.th, y5.th, R.cth, h, tol);
+    const double rr = Cubic(R.r, R.k.r, y5.r, k7.r, h).at(sd);
+    return rr >= R.r_in && rr <= R.r_out;
 }
 
 // An equatorial crossing on a step that does not end the ray.  It counts, and
@@ -890,28 +937,23 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     const bool dk = R.max_hits > 0 && ((R.cth > 0.0 && c5 <= 0.0) || (R.cth < 0.0 && c5 >= 0.0));
     if (hz | es) {
         // terminal step: the finishing pass locates the root (and a crossing
-        // of the equator before it) on the step's cubics
-        double* t = R.rec + REC_TERM;
-        t[0] = R.r;
-        t[1] = R.k.r;
-        t[2] = y5.r;
-        t[3] = k7.r;
-        t[4] = R.th;
-        t[5] = R.k.th;
-        t[6] = y5.th;
-        t[7] = k7.th;
-        t[8] = R.ph;
-        t[9] = R.k.ph;
-        t[10] = y5.ph;
-        t[11] = k7.ph;
-        t[12] = h;
-        t[13] = R.lam;
-        t[14] = hz ? r_stop : r_esc;   // at most one radial event brackets a root in one step
-        t[15] = R.cth;
+        // of the equator before it) on the step's cubics; at most one radial
+        // event brackets a root in one step
+        terminal_step(R, h, y5, k7, hz ? r_stop : r_esc);
         ray_finish(R, A, hz ? CLS_CAPTURED : CLS_ESCAPED, (hz ? 1 : 2) | (dk ? 4 : 0));
         return true;
     }
-    if (dk) disk_crossing(R, h, y5, k7, 0.125 * A.event_tol);
+    if (dk) {
+        if (R.opaque) {
+            if (opaque_hit(R, h, y5, k7, 0.125 * A.event_tol)) {
+                terminal_step(R, h, y5, k7, 0.0);
+                ray_finish(R, A, CLS_ON_DISK, 8);
+                return true;
+            }
+        } else {
+            disk_crossing(R, h, y5, k7, 0.125 * A.event_tol);
+        }
+    }
 
     R.lam += h;
     R.t = y5.t;
@@ -1121,35 +1163,48 @@ __global__ void finish_kernel(const DevJob* jobs, const JobConst* jc, int job0)
     }
     const double* t = rec + REC_TERM;
     const int code = (int)rec[REC_CODE];
+    int cls = iv[0];
     double fr = t[0], fth = t[4], fph = t[8];
-    if (code & 3) {
+    if (code & 11) {
         const double h = t[12];
         const Cubic pr(t[0], t[1], t[2], t[3], h);
         const Cubic pth(t[4], t[5], t[6], t[7], h);
-        const double s_term = locate_root(pr, t[14], (code & 3) == 1, h, tol);
+        // code 8: the crossing itself ends the ray (opaque disk); it was
+        // counted in the integrator and lies on the disk
+        double s_end = (code & 8) ? equator_root(pth, t[4], t[6], t[15], h, tol)
+                                  : locate_root(pr, t[14], (code & 3) == 1, h, tol);
+        bool hit = (code & 8) != 0;
+        double s_disk = s_end;
         if (code & 4) {
             // a crossing at or before the terminal root counts, one after it does not
-            const double s_disk = equator_root(pth, t[4], t[6], t[15], h, tol);
-            if (s_disk <= s_term) {
+            s_disk = equator_root(pth, t[4], t[6], t[15], h, tol);
+            if (s_disk <= s_end) {
                 n_cross++;
                 const double rr = pr.at(s_disk);
-                if (n < J.max_hits && rr >= C.r_in && rr <= J.disk_r_out) {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        if (k == n) {
-                            hr[k] = rr;
-                            hl[k] = fma(s_disk, h, t[13]);
-                            ho[k] = n_cross;
-                        }
-                    n++;
+                hit = n < J.max_hits && rr >= C.r_in && rr <= J.disk_r_out;
+                if (hit && (J.disk_flags & DISK_OPAQUE)) {
+                    // the opaque disk comes first: the ray ends on it
+                    s_end = s_disk;
+                    cls = CLS_ON_DISK;
                 }
             }
         }
-        fr = pr.at(s_term);
-        fth = pth.at(s_term);
-        fph = Cubic(t[8], t[9], t[10], t[11], h).at(s_term);
+        if (hit) {
+            const double rr = pr.at(s_disk);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k == n) {
+                    hr[k] = rr;
+                    hl[k] = fma(s_disk, h, t[13]);
+                    ho[k] = n_cross;
+                }
+            n++;
+        }
+        fr = pr.at(s_end);
+        fth = pth.at(s_end);
+        fph = Cubic(t[8], t[9], t[10], t[11], h).at(s_end);
     }
-    J.cls[q] = iv[0];
+    J.cls[q] = cls;
     J.n_hits[q] = n;
     J.final_rtp[3 * q + 0] = fr;
     J.final_rtp[3 * q + 1] = fth;
@@ -1174,7 +1229,7 @@ __global__ void finish_kernel(const DevJob* jobs, const JobConst* jc, int job0)
             g = redshift(J.a, hr[k], p[0], p[3]);
             const double F = nt_flux_pre(J.a, C.x0, C.xi, C.coef, hr[k]);
             const double g2 = g * g;
-            flux = g2 * g2 * F;
+            flux = (J.disk_flags & DISK_INTRINSIC) ? F : g2 * g2 * F;
             inten += flux;
         }
         J.hit_r[3 * q + k] = hr[k];

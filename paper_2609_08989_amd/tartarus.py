@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtartarus.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_TOO_LARGE, E_NOT_FOUND, E_AGAIN = 0, -1, -2, -3, -4, -5, -6
-ESCAPED, CAPTURED, FAILED = 0, 1, 2
+ESCAPED, CAPTURED, FAILED, ON_DISK = 0, 1, 2, 3
+SHADE_OBSERVED, SHADE_INTRINSIC = 0, 1
 METRIC_KERR, METRIC_TABLE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 ORDER_DEFAULT, ORDER_PIXEL, ORDER_COST = 0, 1, 2
@@ -42,7 +43,8 @@ class Camera(C.Structure):
 
 
 class Disk(C.Structure):
-    _fields_ = [("r_in", C.c_double), ("r_out", C.c_double), ("max_hits", C.c_int)]
+    _fields_ = [("r_in", C.c_double), ("r_out", C.c_double), ("max_hits", C.c_int), ("opaque", C.c_int),
+                ("shading", C.c_int)]
 
 
 class Solver(C.Structure):
@@ -130,8 +132,8 @@ def make_camera(c: dict) -> Camera:
 
 def make_disk(d: dict | None) -> Disk:
     if d is None:
-        return Disk(0.0, 0.0, 0)
-    return Disk(d.get("r_in", 0.0), d["r_out"], d.get("max_hits", 3))
+        return Disk(0.0, 0.0, 0, 0, 0)
+    return Disk(d.get("r_in", 0.0), d["r_out"], d.get("max_hits", 3), d.get("opaque", 0), d.get("shading", 0))
 
 
 def make_solver(s: dict, precision: int = PREC_FP64) -> Solver:

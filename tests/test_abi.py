@@ -67,6 +67,9 @@ def test_validate_accepts_the_workloads(T):
     (lambda m, c, d, s: (setattr(s, "method", 3), setattr(s, "precision", 1)), "mixed needs DP45"),
     (lambda m, c, d, s: (setattr(s, "method", 4), setattr(s, "precision", 1)), "mixed needs DP45"),
     (lambda m, c, d, s: setattr(d, "max_hits", 4), "max_hits"),
+    (lambda m, c, d, s: setattr(d, "opaque", 2), "opaque"),
+    (lambda m, c, d, s: (setattr(d, "opaque", 1), setattr(d, "max_hits", 0)), "opaque needs a hit"),
+    (lambda m, c, d, s: setattr(d, "shading", 2), "shading"),
     (lambda m, c, d, s: setattr(m, "kind", 7), "kind"),
 ])
 def test_validate_rejects(T, mutate, field):

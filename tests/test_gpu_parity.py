@@ -271,6 +271,28 @@ def test_extrapolation_kerr09_512_sampled(T, orc):
     assert np.all(g["cls"] != 2)
 
 
+# ---------------------------------------------------------- rendering variants
+def test_opaque_disk_and_intrinsic_map(T, orc):
+    """The optically thick disk (Sec. 2.3: the first crossing on the disk ends
+    the ray, class ON_DISK) and the intrinsic map (Fig. KerrUHD b: flux F with
+    the shift switched off), each on a ragged 61x47 spin-0.9 image, against
+    the oracle at the FP64 bar."""
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=61, ny=47, theta_obs=75.0 * math.pi / 180)
+    for extra in (dict(opaque=1), dict(shading=1), dict(opaque=1, shading=1)):
+        disk = dict(w["disk"], **extra)
+        say("case kerr09 61x47 disk", extra)
+        g, o = full_image_parity(T, orc, w["a"], cam, disk, w["solver"])
+        if extra.get("opaque"):
+            on = o["cls"] == orc.ON_DISK
+            assert on.sum() > 300 and np.array_equal(g["cls"] == 3, on)
+            assert np.all(g["n_hits"][on] == 1)
+            assert np.abs(np.cos(g["final_rtp"][on, 1])).max() < 1e-11
+        if extra.get("shading"):
+            m = g["n_hits"] > 0
+            assert np.all(g["hit_flux"][m, 0] > 0) and np.all(g["hit_g"][m, 0] > 0)
+
+
 # ------------------------------------------------------------------ Verlet
 VERLET_CAM = dict(r_obs=100.0, theta_obs=math.pi / 3, nx=24, ny=24, alpha_min=-12.0, alpha_max=12.0,
                   beta_min=-12.0, beta_max=12.0)
