@@ -190,9 +190,12 @@ typedef struct {
  * row-major); TARTARUS_ORDER_COST first sorts them into buckets by how close
  * they pass to the critical curve (the spherical photon orbits, which the
  * rays that take the most steps wind around) and starts the closest first, so
- * that the longest rays do not start last and finish alone.  The default
- * (0) is COST for traces of at least 4096 rays, else PIXEL. */
-enum { TARTARUS_ORDER_DEFAULT = 0, TARTARUS_ORDER_PIXEL = 1, TARTARUS_ORDER_COST = 2 };
+ * that the longest rays do not start last and finish alone; TARTARUS_ORDER_TILE
+ * hands them out by 8 x 8 pixel tiles (tiles row-major, pixels row-major in a
+ * tile; ragged edge tiles are smaller), so that a wavefront's rays are
+ * neighbours on the sky and follow similar paths.  The default (0) is COST
+ * for traces of at least 4096 rays, else PIXEL. */
+enum { TARTARUS_ORDER_DEFAULT = 0, TARTARUS_ORDER_PIXEL = 1, TARTARUS_ORDER_COST = 2, TARTARUS_ORDER_TILE = 3 };
 
 typedef struct {
     int block_threads;     /* 64, 128 or 256                                        */

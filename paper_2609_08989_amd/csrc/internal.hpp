@@ -102,7 +102,7 @@ struct LaunchArgs {
     const long long* dir_begin;     // null: look up jobs[].ray_begin directly
     const int* dir_job;
     int ndir;
-    int pad2;
+    int tile;                       // 1: queue positions run over 8 x 8 pixel tiles of each camera
     // queue position -> ray index (relative to first_ray); null: identity
     const unsigned int* order;
     // serving: rays still to finish, per job-table entry (null: not counted)

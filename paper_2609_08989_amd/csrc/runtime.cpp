@@ -318,8 +318,15 @@ tartarus_launch default_launch(int kind, int prec, int method)
     return L;
 }
 
-int resolve_launch(int kind, int prec, int method, const tartarus_launch* req, tartarus_launch& L, int& grid)
+int resolve_launch(int kind, int prec, int method, const tartarus_launch* req_in, tartarus_launch& L, int& grid)
 {
+    // req_in may point at L itself: read the request before L is overwritten
+    tartarus_launch req_copy;
+    const tartarus_launch* req = nullptr;
+    if (req_in) {
+        req_copy = *req_in;
+        req = &req_copy;
+    }
     L = default_launch(kind, prec, method);
     if (req) {
         if (req->block_threads > 0) L.block_threads = req->block_threads;
@@ -328,7 +335,7 @@ int resolve_launch(int kind, int prec, int method, const tartarus_launch* req, t
         if (req->refill_min > 0) L.refill_min = req->refill_min;
         if (req->order > 0) L.order = req->order;
     }
-    if (L.order < 0 || L.order > TARTARUS_ORDER_COST) return fail(TARTARUS_E_INVALID, "unknown queue order");
+    if (L.order < 0 || L.order > TARTARUS_ORDER_TILE) return fail(TARTARUS_E_INVALID, "unknown queue order");
     if (L.block_threads != 64 && L.block_threads != 128 && L.block_threads != 256)
         return fail(TARTARUS_E_INVALID, "block_threads must be 64, 128 or 256");
     if (L.refill_min < 1 || L.refill_min > 64) return fail(TARTARUS_E_INVALID, "refill_min must be in 1..64");
@@ -410,6 +417,7 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
         HIP_TRY(tartarus_launch_order(&A, n, key, count, cursor, order, stream));
         A.order = order;
     }
+    A.tile = L.order == TARTARUS_ORDER_TILE ? 1 : 0;
     HIP_TRY(tartarus_launch_trace(kind, prec, method, &A, grid, L.block_threads, stream));
     for (int c0 = 0; c0 < ncams; c0 += 65535)
         HIP_TRY(tartarus_launch_finish(&A, c0, std::min(65535, ncams - c0), per, stream));
@@ -589,7 +597,7 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
             if ((rc = time_trace(metric, cams, ncams, disk, solver, out, L, stream, ms))) return rc;
             if (ms < best_ms) { best_ms = ms; cur = L; }
         }
-        for (int o : {(int)TARTARUS_ORDER_PIXEL, (int)TARTARUS_ORDER_COST}) {
+        for (int o : {(int)TARTARUS_ORDER_PIXEL, (int)TARTARUS_ORDER_COST, (int)TARTARUS_ORDER_TILE}) {
             tartarus_launch L = cur;
             L.order = o;
             float ms = 0.f;

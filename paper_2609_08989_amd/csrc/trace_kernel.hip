@@ -309,13 +309,35 @@ __device__ __forceinline__ int find_job(const LaunchArgs& A, const JobDir& D, lo
 // ---------------------------------------------------------------------------
 // Returns false when the ray's job has been cancelled (serving): then the ray
 // is not traced.
+// Pixel of queue position q when a camera's rays are handed out by 8 x 8 tiles:
+// tile rows of 8 pixel rows (the last one h = ny - 8 ty rows high), tiles
+// row-major within a tile row (each 8 wide but the last, nx - 8 tx), pixels
+// row-major within a tile.  Tile (tx, ty) starts at 8 ty nx + 8 tx h.
+__device__ __forceinline__ long long tile_pixel(long long q, int nx, int ny)
+{
+    const long long band = 8ll * nx;
+    long long ty = q / band;
+    const long long ty_last = (ny - 1) / 8;
+    if (ty > ty_last) ty = ty_last;
+    const long long h = ny - 8 * ty < 8 ? ny - 8 * ty : 8;
+    const long long r = q - ty * band;
+    long long tx = r / (8 * h);
+    const long long tx_last = (nx - 1) / 8;
+    if (tx > tx_last) tx = tx_last;
+    const long long inner = r - tx * 8 * h;
+    const long long w = nx - 8 * tx < 8 ? nx - 8 * tx : 8;
+    const long long jj = inner / w, ii = inner - jj * w;
+    return (8 * ty + jj) * nx + 8 * tx + ii;
+}
+
 template <int KIND>
 __device__ bool ray_init(Ray& R, long long gid, const LaunchArgs& A, const JobDir& D, const MetricOps<KIND>& M)
 {
     const int jb = find_job(A, D, gid);
     const DevJob& J = A.jobs[jb];
     const JobConst& C = A.jc[jb];
-    const long long pix = gid - J.ray_begin;
+    const long long pos = gid - J.ray_begin;
+    const long long pix = A.tile ? tile_pixel(pos, J.nx, J.ny) : pos;
     double al, be, p[4];
     pixel_coords(J, pix, al, be);
     pixel_momentum(C, J.r_obs, al, be, p);

@@ -21,7 +21,7 @@ ESCAPED, CAPTURED, FAILED, ON_DISK = 0, 1, 2, 3
 SHADE_OBSERVED, SHADE_INTRINSIC = 0, 1
 METRIC_KERR, METRIC_TABLE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
-ORDER_DEFAULT, ORDER_PIXEL, ORDER_COST = 0, 1, 2
+ORDER_DEFAULT, ORDER_PIXEL, ORDER_COST, ORDER_TILE = 0, 1, 2, 3
 METHOD_DP45, METHOD_CK45, METHOD_RKF45, METHOD_GBS, METHOD_VERLET = 0, 1, 2, 3, 4
 
 

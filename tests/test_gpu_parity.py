@@ -369,9 +369,23 @@ def test_launch_shape_invariance(T):
     ref = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], launch=T.make_launch(order=T.ORDER_PIXEL))
     for bt, bpc, ch, rf, od in ((64, 1, 64, 1, T.ORDER_COST), (128, 0, 1024, 32, T.ORDER_PIXEL),
                                 (256, 1, 96, 64, T.ORDER_COST), (256, 2, 4096, 8, T.ORDER_PIXEL),
-                                (256, 0, 64, 4, T.ORDER_COST), (256, 0, 64, 4, T.ORDER_DEFAULT)):
+                                (256, 0, 64, 4, T.ORDER_COST), (256, 0, 64, 4, T.ORDER_DEFAULT),
+                                (256, 1, 1, 4, T.ORDER_TILE), (64, 2, 16, 1, T.ORDER_TILE)):
         say("launch", bt, bpc, ch, rf, od)
         g = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], launch=T.make_launch(bt, bpc, ch, rf, od))
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), k
+
+
+def test_tile_order_ragged_cameras(T):
+    """8 x 8 tile order on cameras whose sides are not multiples of 8 (edge
+    tiles are smaller), three cameras in one trace: every pixel is traced once
+    and gives the bits of pixel order."""
+    w = W.WORKLOADS["kerr09_512"]
+    cams = [dict(w["cameras"][0], nx=45, ny=29, theta_obs=t) for t in (0.6, 1.0, 1.4)]
+    ref = gpu_trace(T, w["a"], cams, w["disk"], w["solver"], launch=T.make_launch(order=T.ORDER_PIXEL))
+    for shape in ((256, 1, 1, 4, T.ORDER_TILE), (128, 0, 7, 2, T.ORDER_TILE)):
+        g = gpu_trace(T, w["a"], cams, w["disk"], w["solver"], launch=T.make_launch(*shape))
         for k in ref:
             assert np.array_equal(ref[k], g[k]), k
 
@@ -387,7 +401,7 @@ def test_autotune_picks_a_valid_shape_with_identical_results(T):
     best = T.tartarus_autotune(T.make_metric(w["a"]), [T.make_camera(cam)], T.make_disk(w["disk"]),
                                T.make_solver(w["solver"]), out)
     say("tuned", best.block_threads, best.blocks_per_cu, best.chunk, best.refill_min, best.order)
-    assert best.order in (T.ORDER_DEFAULT, T.ORDER_PIXEL, T.ORDER_COST)
+    assert best.order in (T.ORDER_PIXEL, T.ORDER_COST, T.ORDER_TILE)
     assert best.block_threads in (64, 128, 256)
     assert best.blocks_per_cu >= 0 and best.chunk >= 1 and 1 <= best.refill_min <= 64
     tuned_out = T.to_numpy(out)
