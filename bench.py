@@ -129,10 +129,13 @@ def cpu_baseline(w, solver, seconds: float) -> dict:
                       f"plain FP64 C oracle, OpenMP over pixels, {dt:.1f} s"}
 
 
-def workload_legs(T, torch, W, out_cache, steps: int = 2) -> dict:
-    """rays/s of the other image workloads (default launch, rtol 1e-8): the
-    Schwarzschild shadow, the a = 0.998 2048^2 scene in FP64 and mixed, the
-    paper's OSIRIS calibration scene, and the 64-camera tabulated-metric batch."""
+def workload_legs(T, torch, W, out_cache, steps: int = 2, autotune: bool = True) -> dict:
+    """rays/s of the other image workloads (rtol 1e-8): the Schwarzschild
+    shadow, the a = 0.998 2048^2 scene in FP64 and mixed, the paper's OSIRIS
+    calibration scene, and the 64-camera tabulated-metric batch.  Each image
+    scene is autotuned first (untimed); the tabulated batch (0.7 s a launch)
+    uses the shape measured best for it (256 threads, 2 blocks per CU, pixel
+    order)."""
     legs = {}
     for name, prec in (("schwarzschild_64", T.PREC_FP64), ("kerr0998_2048", T.PREC_FP64),
                        ("kerr0998_2048", T.PREC_MIXED), ("osiris_1024", T.PREC_FP64),
@@ -154,12 +157,19 @@ def workload_legs(T, torch, W, out_cache, steps: int = 2) -> dict:
         out = out_cache[n]
         la = (metric, cams, T.make_disk(w["disk"]), T.make_solver(w["solver"], prec))
         log("bench: workload", name, "mixed" if prec else "fp64")
-        wl, km = time_leg(T, torch, la, out, steps, 1)
+        if "table" in w:
+            launch = T.make_launch(256, 2, 1, 4, T.ORDER_PIXEL)
+        elif autotune:
+            launch = T.tartarus_autotune(*la, out)
+        else:
+            launch = None
+        wl, km = time_leg(T, torch, la, out, steps, 1, launch)
         o = T.to_numpy(out)
         att = o["n_accept"] + o["n_reject"]
         legs[f"{name}_{'mixed' if prec else 'fp64'}"] = {
             "rays": n, "rays_per_s": n * steps / wl, "kernel_ms": km, "attempts_per_ray": float(att.mean()),
-            "failed_rays": int((o["cls"] == 2).sum())}
+            "failed_rays": int((o["cls"] == 2).sum()),
+            "launch": dict(zip(SHAPE_KEYS, shape(launch))) if launch is not None else "default"}
     return legs
 
 
@@ -355,7 +365,7 @@ def main():
                                     "steps_per_s": float(ol["n_accept"].sum()) * 2 / wl,
                                     "h_gate_max": float(ol["h_gate"][ol["cls"] != 2].max()),
                                     "failed_rays": int((ol["cls"] == 2).sum())}
-        legs.update(workload_legs(T, torch, W, {}))
+        legs.update(workload_legs(T, torch, W, {}, autotune=not args.no_autotune))
         legs["mixed_over_fp64_same_rtol"] = legs["mixed_rtol1e-8"]["rays_per_s"] / legs["fp64_rtol1e-8"]["rays_per_s"]
         legs["mixed_rtol1e-8_over_fp64_gate"] = legs["mixed_rtol1e-8"]["rays_per_s"] / value
         result["legs"] = legs
