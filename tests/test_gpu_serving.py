@@ -115,6 +115,38 @@ def test_budget_too_small(T):
     assert e.value.code == T.E_TOO_LARGE
 
 
+@pytest.mark.parametrize("method", [3, 4], ids=["gbs", "verlet"])
+def test_other_methods_and_disk_variants_served(T, method):
+    """A session of Gragg-Bulirsch-Stoer (or fixed-step Verlet) requests whose
+    disks differ per request (transparent, opaque, intrinsic shading): each
+    request's outputs are the bits of tracing it alone."""
+    reqs = stream_requests(4, seed=30 + method, res=(24, 40))
+    variants = ({}, {"opaque": 1}, {"shading": 1}, {"opaque": 1, "shading": 1})
+    outs, tickets = [], []
+    for r, v in zip(reqs, variants):
+        r["disk"] = dict(r["disk"], **v)
+        r["solver"] = dict(r["solver"], method=method)
+        if method == 4:
+            # fixed step 0.05 M from r_obs: a short, converging Verlet trace
+            r["camera"] = dict(r["camera"], r_obs=60.0, alpha_min=-8.0, alpha_max=8.0, beta_min=-8.0, beta_max=8.0)
+            r["solver"] = dict(r["solver"], h0_frac=0.05 / 60.0, horizon_factor=1.1, r_escape=66.0)
+        cam = r["camera"]
+        o = T.alloc_outputs(cam["nx"] * cam["ny"])
+        outs.append(o)
+        tickets.append(T.tartarus_submit(T.make_metric(r["a"]), T.make_camera(cam), T.make_disk(r["disk"]),
+                                         T.make_solver(r["solver"]), o))
+    for t in tickets:
+        T.tartarus_wait(t, 120000)
+        assert T.tartarus_poll(t) == 2
+    for r, o in zip(reqs, outs):
+        g = T.to_numpy(o)
+        ref = alone(T, r, 0)
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (r["id"], k)
+        if r["disk"].get("opaque"):
+            assert np.all(g["n_hits"] <= 1)
+
+
 def test_request_larger_than_the_lane_count(T):
     """More rays than device lanes: lanes refill in partial waves and park at
     epoch ends; every ray id handed out must be traced (no request may stall)."""
