@@ -9,9 +9,10 @@
  *   - Hamilton's equations of H = 1/2 g^{mu nu} p_mu p_nu (Sec. 2.1, Eqs. (1)-(3)),
  *     on the 8-D state q = [t, r, theta, phi, p_t, p_r, p_theta, p_phi];
  *   - an adaptive embedded Dormand-Prince 5(4) step with per-ray error control
- *     (Sec. 3.2);
- *   - horizon, escape and equatorial-disk events refined by bisection on the
- *     step's cubic Hermite interpolant (Sec. 3.2);
+ *     (Sec. 3.2); the paper's other integrators (Cash-Karp and Fehlberg 5(4),
+ *     Gragg-Bulirsch-Stoer, fixed-step Verlet) through tartarus_solver.method;
+ *   - horizon, escape and equatorial-disk events located on the step's cubic
+ *     Hermite interpolant (Sec. 3.2);
  *   - Novikov-Thorne shading g^4 F(r) at each recorded disk crossing
  *     (Secs. 2.3-2.4, Eqs. (11)-(16));
  *   - the constraint residual |H| at every accepted step (Sec. 4.1, Eq. (17)).
@@ -37,11 +38,13 @@
  *     rejection; first step h0_frac * r_obs;
  *   - events on each accepted step: horizon when r falls to horizon_factor *
  *     r_+ (or the table's inner radius, if larger), escape when r rises to
- *     r_escape, disk crossing when cos(theta) changes sign; bisection for the
- *     smallest n >= 0 with h / 2^n <= event_tol, root at the bracket midpoint;
+ *     r_escape, disk crossing when cos(theta) changes sign; the root is
+ *     located on the interpolant to well within event_tol in lambda
+ *     (safeguarded Newton iteration on the cubic, bracket kept; the paper
+ *     bisects to ~1e-12, and the two roots differ by less than that);
  *   - emitter: prograde Keplerian Omega = 1 / (r^{3/2} + a); the first up to
  *     max_hits (<= 3) crossings inside [r_in, r_out] are recorded; the ray
- *     continues to a terminal event.
+ *     continues to a terminal event unless the disk is opaque.
  */
 #ifndef TARTARUS_H
 #define TARTARUS_H
@@ -165,7 +168,7 @@ typedef struct {
  * arrays marked [3] hold three doubles / ints per ray (hit slots).  All are
  * required.  Unused hit slots are written as zero. */
 typedef struct {
-    int32_t* cls;          /* TARTARUS_ESCAPED / CAPTURED / FAILED                    */
+    int32_t* cls;          /* TARTARUS_ESCAPED / CAPTURED / FAILED / ON_DISK          */
     int32_t* n_hits;       /* recorded disk hits, 0..max_hits                        */
     double* final_rtp;     /* [3] r, theta, phi at the terminal event (FAILED: last state) */
     double* h_drift;       /* max |H| over the accepted states (Eq. (17))            */

@@ -1,28 +1,33 @@
-// trace_kernel.hip -- the persistent ray-queue integrator (gfx950) and its
-// set-up and shading passes.
+// trace_kernel.hip -- the persistent ray-queue integrator (gfx950) and the
+// passes around it.
 //
-// A trace is three launches on one stream:
+// A trace is a short sequence of launches on one stream:
 //   1. job_setup: per camera / request, the observer's metric and ZAMO tetrad
 //      (Sec. 2.2), r_+, the disk's inner edge and the Page-Thorne constants.
-//   2. trace_persistent: one lane integrates one ray at a time.  A wavefront
-//      takes ray ids from a global atomic queue head in chunks; when a lane's
-//      ray terminates, its outputs are written by ray id and the lane is
-//      refilled, so divergent step counts do not leave lanes idle until the
-//      slowest ray of the wave is done.  Per ray: camera initial conditions,
-//      Dormand-Prince 5(4) steps with the elementary controller, horizon /
-//      escape / equatorial events on accepted steps located on the step's
-//      cubic Hermite interpolant, and the constraint residual |H| at each
-//      accepted state (Secs. 2.2, 3.2, 4.1).
-//   3. shade: redshift g (Eq. (15)) and Novikov-Thorne flux g^4 F(r)
-//      (Eqs. (11), (16)) of every recorded disk crossing, and the pixel
-//      intensity; a coalesced pass over the rays instead of divergent work
-//      inside the integrator.
+//   2. order_keys / order_scan / order_scatter (traces of >= 4096 rays by
+//      default): the cost-ordered queue, rays nearest the critical curve first.
+//   3. trace_persistent<KIND, PREC, METHOD>: one lane integrates one ray at a
+//      time.  A wavefront takes ray ids from a global atomic queue head; when
+//      a lane's ray terminates, the lane is refilled, so divergent step counts
+//      do not leave lanes idle until the slowest ray of the wave is done.  Per
+//      ray: camera initial conditions, steps of the chosen method (Sec. 3.2:
+//      Dormand-Prince, Cash-Karp or Fehlberg 5(4) with the elementary
+//      controller, Gragg-Bulirsch-Stoer extrapolation, or fixed-step Verlet),
+//      the constraint residual |H| at each accepted state (Sec. 4.1), and the
+//      detection of horizon / escape / equatorial events on accepted steps.
+//      The integrator leaves each event's step (its cubic Hermite data) in
+//      the ray's record instead of locating it, except where a crossing
+//      straddles a disk edge.
+//   4. finish_kernel: one thread per ray locates the recorded roots on the
+//      same cubics, writes every output, and shades the disk hits with g
+//      (Eq. (15)) and g^4 F(r) (Eqs. (11), (16)).
 // Per-ray arithmetic never depends on other lanes, so results are
-// bit-identical for every launch shape and batch composition.
+// bit-identical for every launch shape, queue order and batch composition.
 //
-// Precision: PREC = 0 evaluates every stage in FP64.  PREC = 1 evaluates the
-// stages of far-field steps in FP32 (stages32) while the state update, error
-// norm, controller, events and shading stay FP64.
+// KIND 0 is analytic Kerr, 1 the tabulated metric.  PREC = 0 evaluates every
+// stage in FP64; PREC = 1 evaluates the stages of far-field steps in FP32
+// (stages32) while the state update, error norm, controller, events and
+// shading stay FP64.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
