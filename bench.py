@@ -25,6 +25,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -62,13 +63,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "trace_persistent_fp64_kerr09_512.traffic.json")
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
 def kernel_source_hash() -> str:
-    """sha256 over the device sources; HBM traffic measured for other sources is stale."""
+    """sha256 over the device sources with comments and blank lines removed;
+    HBM traffic measured for other code is stale."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(HERE, "paper_2609_08989_amd", "csrc", "*.h*"))):
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            code = _COMMENT.sub("", fh.read())
+        h.update("\n".join(ln.rstrip() for ln in code.splitlines() if ln.strip()).encode())
     return h.hexdigest()
 
 
