@@ -78,18 +78,20 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(launch_shape):
+def measured_traffic():
     """HBM bytes per launch of the headline kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), if they were taken on these
-    kernel sources with this launch shape; else None."""
+    kernel sources; else None.  The bytes are the per-ray records, outputs and
+    job tables of the image, which do not depend on the launch shape; the
+    shape they were measured at is returned with them."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except OSError:
-        return None
-    if t.get("source_sha256") != kernel_source_hash() or t.get("launch") != launch_shape:
-        return None
-    return float(t["fetch_bytes"] + t["write_bytes"])
+        return None, None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None, None
+    return float(t["fetch_bytes"] + t["write_bytes"]), t.get("launch")
 
 
 def shape(L):
@@ -179,13 +181,17 @@ def workload_legs(T, torch, W, out_cache, steps: int = 2, autotune: bool = True)
     return legs
 
 
-def serving_leg(T, torch, W, n_requests: int, loads=(0.5, 0.8, 0.95), budget_gib: int = 8) -> dict:
+def serving_leg(T, torch, W, n_requests: int, loads=(0.5, 0.8, 0.95), budget_gib: int = 8,
+                arrival_order_load: float = 0.8) -> dict:
     """Poisson streams of image requests (resolution uniform over 64^2..1024^2,
     spin, inclination, disk size drawn per request) submitted at their arrival
     times through tartarus_submit under an HBM budget that makes admission
     bind; latency = done - submit per request.  The offered load is a fraction
     of the server's own throughput, measured first on a burst of requests from
-    the same distribution (another seed); stream k uses seed k."""
+    the same distribution (another seed); stream k uses seed k.  The queue
+    hands out the smallest admitted request's rays first; one more stream, at
+    arrival_order_load with the seed of that load, runs with arrival order for
+    comparison."""
     mk = lambda r: (T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
                     T.make_solver(r["solver"]))
     T.tartarus_shutdown()
@@ -201,12 +207,16 @@ def serving_leg(T, torch, W, n_requests: int, loads=(0.5, 0.8, 0.95), budget_gib
     del bouts
     mean_rays = float(np.mean([r * r for r in W.RESOLUTIONS]))
     runs = []
-    for seed, load in enumerate(loads):
+    plan = [(seed, load, T.SERVE_SMALLEST_FIRST) for seed, load in enumerate(loads)]
+    if arrival_order_load in loads:
+        plan.append((loads.index(arrival_order_load), arrival_order_load, T.SERVE_ARRIVAL))
+    for seed, load, policy in plan:
+        T.tartarus_serving_order(policy)
         rate = load * capacity / mean_rays
         reqs = W.request_stream(seed, n_requests, rate)
         outs = [T.alloc_outputs(r["camera"]["nx"] * r["camera"]["ny"]) for r in reqs]
         torch.cuda.synchronize()
-        log("bench: serving load", load, "requests", n_requests)
+        log("bench: serving load", load, "requests", n_requests, "order", policy)
         tickets = []
         t0 = time.perf_counter()
         for r, o in zip(reqs, outs):
@@ -223,6 +233,7 @@ def serving_leg(T, torch, W, n_requests: int, loads=(0.5, 0.8, 0.95), budget_gib
         span = (stamps[:, 2].max() - stamps[:, 0].min()) * 1e-9
         failed = int(sum(int((T.to_numpy({"cls": o["cls"]})["cls"] == 2).sum()) for o in outs))
         runs.append({"load": load, "seed": seed, "requests": len(reqs), "arrival_rate_per_s": rate,
+                     "order": "smallest_first" if policy == T.SERVE_SMALLEST_FIRST else "arrival",
                      "p50_latency_ms": float(np.percentile(lat_ms[warm:], 50)),
                      "p99_latency_ms": float(np.percentile(lat_ms[warm:], 99)),
                      "max_latency_ms": float(lat_ms[warm:].max()), "rays_per_s": rays / span,
@@ -230,13 +241,14 @@ def serving_leg(T, torch, W, n_requests: int, loads=(0.5, 0.8, 0.95), budget_gib
         del outs
     T.tartarus_shutdown()
     T.tartarus_init(0, 0)
-    ref = min(runs, key=lambda x: abs(x["load"] - 0.8))
+    T.tartarus_serving_order(T.SERVE_SMALLEST_FIRST)
+    ref = min((x for x in runs if x["order"] == "smallest_first"), key=lambda x: abs(x["load"] - 0.8))
     return {"requests_per_load": n_requests, "capacity_rays_per_s": capacity, "precision": "fp64",
             "rtol": W.solver()["rtol"], "hbm_budget_gib": budget_gib,
             "p50_latency_ms": ref["p50_latency_ms"], "p99_latency_ms": ref["p99_latency_ms"], "load": ref["load"],
             "by_load": runs,
             "note": "latency = completion - submission; first 10 requests of each stream are warm-up; "
-                    "load = fraction of the burst capacity; headline p50/p99 at load 0.8"}
+                    "load = fraction of the burst capacity; headline p50/p99 at load 0.8, smallest request first"}
 
 
 def main():
@@ -304,6 +316,7 @@ def main():
     flops = algorithmic_flops(o)
     achieved = flops / (kern_ms * 1e-3) / 1e12
     att = o["n_accept"] + o["n_reject"]
+    traffic_bytes, traffic_shape = measured_traffic()
     result = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -314,7 +327,7 @@ def main():
                    "failed_rays": int((o["cls"] == 2).sum()), "attempts_per_ray": float(att.mean())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": measured_traffic(",".join(str(v) for v in tuned.get("fp64", []))),
+                     "traffic": traffic_bytes, "traffic_launch_shape": traffic_shape,
                      "kernel": "trace_persistent<0,0> (analytic Kerr, FP64)",
                      "kernel_ms": kern_ms, "flop_per_launch": flops,
                      "flop_per_attempt": FLOP_ATTEMPT},

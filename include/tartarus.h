@@ -261,6 +261,18 @@ int tartarus_build_kerr_table(double a, int nr, int nth, double r_min, double r_
  * of the first request fixes rtol/atol/... for the session; later requests
  * must use the same solver (else E_INVALID).  Output buffers must stay alive
  * until poll reports done or cancel returns. */
+
+/* Hand-out order of the serving queue's unstarted rays, applied from the next
+ * epoch on: TARTARUS_SERVE_SMALLEST_FIRST (default) gives lanes to the rays of
+ * the admitted request with the fewest rays first, so small images finish
+ * within a few epochs of their arrival while large ones run behind them;
+ * TARTARUS_SERVE_ARRIVAL hands them out in admission order.  Rays already on
+ * a lane always run to their end, and results do not depend on the order.
+ * E_INVALID for another value, E_DEVICE before tartarus_init. */
+#define TARTARUS_SERVE_SMALLEST_FIRST 0
+#define TARTARUS_SERVE_ARRIVAL 1
+int tartarus_serving_order(int order);
+
 int tartarus_submit(const tartarus_metric* metric, const tartarus_camera* cam, const tartarus_disk* disk,
                     const tartarus_solver* solver, const tartarus_outputs* out, uint64_t* ticket);
 

@@ -109,6 +109,13 @@ struct LaunchArgs {
     unsigned int* remaining;
     // tabulated metric interleaved by grid point (the integrator reads this)
     const double* table_inter;
+    // serving: queue positions run over nseg segments, segment k covering
+    // positions [seg_q[k], seg_q[k+1]) and rays seg_ray[k] + (q - seg_q[k])
+    // (absolute ray indices); nseg = 0: rays first_ray + q
+    const long long* seg_q;         // [nseg + 1]
+    const long long* seg_ray;       // [nseg]
+    int nseg;
+    int pad3;
 };
 
 constexpr int SLOT_DOUBLES = 32;

@@ -19,6 +19,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/tartarus.h"
@@ -680,6 +681,7 @@ struct Request {
     long long ray_begin = 0;
     double* rec = nullptr;  // device records of its rays while admitted
     long long rec_rays = 0; // capacity of rec in rays
+    long long started = 0;  // rays already handed out to lanes
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     bool cancel_req = false, cancel_sent = false, cancel_acked = false;
     bool too_large = false;  // can never fit the budget next to the slot arena
@@ -698,8 +700,13 @@ struct Server {
     uint64_t next_ticket = 1;
     uint64_t entry_ticket[kMaxEntries] = {};
     size_t used_bytes = 0;
-    long long next_ray = 0;    // global ray indices handed out so far
-    long long first_ray = 0;   // rays before this index were taken from the queue
+    long long next_ray = 0;    // global ray indices assigned to admitted requests so far
+    int serve_order = TARTARUS_SERVE_SMALLEST_FIRST;
+    long long* dseg_q = nullptr;    // epoch queue segments (see LaunchArgs)
+    long long* dseg_ray = nullptr;
+    long long* hseg_q = nullptr;
+    long long* hseg_ray = nullptr;
+    int seg_entry[kMaxEntries] = {};
     // device resources (owned by the scheduler thread once started)
     bool dev_ready = false;
     hipStream_t stream = nullptr;
@@ -788,6 +795,10 @@ int server_alloc(int prec, int method)
     HIP_TRY(hipMalloc(&S.ddir_job, sizeof(int) * kMaxEntries));
     HIP_TRY(hipHostMalloc(&S.hdir_begin, sizeof(long long) * kMaxEntries, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&S.hdir_job, sizeof(int) * kMaxEntries, hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&S.dseg_q, sizeof(long long) * (kMaxEntries + 1)));
+    HIP_TRY(hipMalloc(&S.dseg_ray, sizeof(long long) * kMaxEntries));
+    HIP_TRY(hipHostMalloc(&S.hseg_q, sizeof(long long) * (kMaxEntries + 1), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&S.hseg_ray, sizeof(long long) * kMaxEntries, hipHostMallocDefault));
     HIP_TRY(hipMalloc(&S.slots, sizeof(double) * SLOT_DOUBLES * S.nslots));
     HIP_TRY(hipMalloc(&S.slot_live, sizeof(unsigned int) * S.nslots));
     HIP_TRY(hipMalloc(&S.dhead, sizeof(unsigned long long)));
@@ -815,6 +826,10 @@ void server_free()
     (void)hipFree(S.ddir_job);
     (void)hipHostFree(S.hdir_begin);
     (void)hipHostFree(S.hdir_job);
+    (void)hipFree(S.dseg_q);
+    (void)hipFree(S.dseg_ray);
+    (void)hipHostFree(S.hseg_q);
+    (void)hipHostFree(S.hseg_ray);
     (void)hipFree(S.slots);
     (void)hipFree(S.slot_live);
     for (auto& kv : S.rec_pool) (void)hipFree(kv.second);
@@ -825,6 +840,7 @@ void server_free()
     if (S.stream) (void)hipStreamDestroy(S.stream);
     S.djobs = nullptr; S.djc = nullptr; S.hjobs = nullptr; S.dremaining = nullptr; S.hremaining = nullptr;
     S.ddir_begin = nullptr; S.ddir_job = nullptr; S.hdir_begin = nullptr; S.hdir_job = nullptr;
+    S.dseg_q = nullptr; S.dseg_ray = nullptr; S.hseg_q = nullptr; S.hseg_ray = nullptr;
     S.slots = nullptr; S.slot_live = nullptr; S.dhead = nullptr; S.hhead = nullptr; S.stream = nullptr;
     S.dev_ready = false;
 }
@@ -921,7 +937,29 @@ int server_round(std::unique_lock<std::mutex>& lk)
         ++nd;
     }
     if (nd == 0) return TARTARUS_OK;
-    const long long first = S.first_ray, total = S.next_ray;
+    // ---- this epoch's queue: the unstarted rays of every live request, one
+    // segment each, smallest request first (or in arrival order); cancelled
+    // requests go first so that their rays drain at once
+    std::vector<std::tuple<int, long long, long long, int>> segs;   // (class, key, ray_begin, entry)
+    for (int e = 0; e < kMaxEntries; ++e) {
+        const uint64_t t = S.entry_ticket[e];
+        if (!t) continue;
+        const Request& R = S.reqs[t];
+        if (R.started >= R.nrays) continue;
+        const long long key = S.serve_order == TARTARUS_SERVE_SMALLEST_FIRST ? R.nrays : R.ray_begin;
+        segs.push_back({S.hjobs[e].cancelled ? 0 : 1, key, R.ray_begin, e});
+    }
+    std::sort(segs.begin(), segs.end());
+    const int nseg = (int)segs.size();
+    S.hseg_q[0] = 0;
+    for (int k = 0; k < nseg; ++k) {
+        const int e = std::get<3>(segs[k]);
+        const Request& R = S.reqs[S.entry_ticket[e]];
+        S.seg_entry[k] = e;
+        S.hseg_ray[k] = R.ray_begin + R.started;
+        S.hseg_q[k + 1] = S.hseg_q[k] + (R.nrays - R.started);
+    }
+    const long long total = S.hseg_q[nseg];
     const tartarus_solver sv = S.solver;
     lk.unlock();
 
@@ -930,6 +968,10 @@ int server_round(std::unique_lock<std::mutex>& lk)
         HIP_TRY(hipMemcpyAsync(S.dremaining + e, S.hremaining + e, sizeof(unsigned int), hipMemcpyHostToDevice, S.stream));
     HIP_TRY(hipMemcpyAsync(S.ddir_begin, S.hdir_begin, sizeof(long long) * nd, hipMemcpyHostToDevice, S.stream));
     HIP_TRY(hipMemcpyAsync(S.ddir_job, S.hdir_job, sizeof(int) * nd, hipMemcpyHostToDevice, S.stream));
+    if (nseg > 0) {
+        HIP_TRY(hipMemcpyAsync(S.dseg_q, S.hseg_q, sizeof(long long) * (nseg + 1), hipMemcpyHostToDevice, S.stream));
+        HIP_TRY(hipMemcpyAsync(S.dseg_ray, S.hseg_ray, sizeof(long long) * nseg, hipMemcpyHostToDevice, S.stream));
+    }
     HIP_TRY(tartarus_launch_fill_u64(S.dhead, 0ull, 1, S.stream));
     LaunchArgs A;
     tartarus_metric m0;
@@ -940,8 +982,11 @@ int server_round(std::unique_lock<std::mutex>& lk)
     A.njobs = kMaxEntries;
     A.chunk = 1;
     A.refill_min = 4;
-    A.first_ray = first;
+    A.first_ray = 0;
     A.total_rays = total;
+    A.seg_q = S.dseg_q;
+    A.seg_ray = S.dseg_ray;
+    A.nseg = nseg;
     A.head = S.dhead;
     A.slots = S.slots;
     A.slot_live = S.slot_live;
@@ -968,8 +1013,14 @@ int server_round(std::unique_lock<std::mutex>& lk)
     if (!done.empty()) HIP_TRY(hipStreamSynchronize(S.stream));
 
     lk.lock();
-    const long long taken = (long long)*S.hhead;
-    S.first_ray = first + std::min(taken, total - first);
+    // the queue was consumed in segment order
+    long long taken = std::min((long long)*S.hhead, total);
+    for (int k = 0; k < nseg && taken > 0; ++k) {
+        Request& R = S.reqs[S.entry_ticket[S.seg_entry[k]]];
+        const long long c = std::min(taken, R.nrays - R.started);
+        R.started += c;
+        taken -= c;
+    }
     for (int e : done) {
         const uint64_t t = S.entry_ticket[e];
         finish_request(S, t, S.reqs[t]);
@@ -1015,6 +1066,16 @@ bool same_solver(const tartarus_solver& a, const tartarus_solver& b)
 }
 
 }  // namespace
+
+extern "C" int tartarus_serving_order(int order)
+{
+    if (order != TARTARUS_SERVE_SMALLEST_FIRST && order != TARTARUS_SERVE_ARRIVAL)
+        return fail(TARTARUS_E_INVALID, "unknown serving order");
+    if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    std::lock_guard<std::mutex> lk(g_srv.mu);
+    g_srv.serve_order = order;
+    return TARTARUS_OK;
+}
 
 extern "C" int tartarus_submit(const tartarus_metric* metric, const tartarus_camera* cam, const tartarus_disk* disk,
                                const tartarus_solver* solver, const tartarus_outputs* out, uint64_t* ticket)
@@ -1148,7 +1209,8 @@ void server_stop()
     S.reqs.clear();
     for (auto& e : S.entry_ticket) e = 0;
     S.used_bytes = 0;
-    S.next_ray = S.first_ray = 0;
+    S.next_ray = 0;
+    S.serve_order = TARTARUS_SERVE_SMALLEST_FIRST;
     S.have_solver = false;
     S.dev_error.clear();
 }

@@ -314,6 +314,22 @@ __device__ __forceinline__ int find_job(const LaunchArgs& A, const JobDir& D, lo
 // ---------------------------------------------------------------------------
 // Returns false when the ray's job has been cancelled (serving): then the ray
 // is not traced.
+// Absolute ray index of queue position q in a serving epoch whose queue runs
+// over segments (the unstarted rays of each live request, in hand-out order):
+// binary search for the segment k with seg_q[k] <= q < seg_q[k + 1].
+__device__ __forceinline__ long long segment_ray(const LaunchArgs& A, long long q)
+{
+    int lo = 0, hi = A.nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.seg_q[mid] <= q)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return A.seg_ray[lo] + (q - A.seg_q[lo]);
+}
+
 // Pixel of queue position q when a camera's rays are handed out by 8 x 8 tiles:
 // tile rows of 8 pixel rows (the last one h = ny - 8 ty rows high), tiles
 // row-major within a tile row (each 8 wide but the last, nx - 8 tx), pixels
@@ -1123,8 +1139,14 @@ trace_persistent(LaunchArgs A)
                     }
                 }
                 if (id >= 0) {
-                    if (A.order) id = (long long)A.order[id];
-                    active = ray_init<KIND>(R, A.first_ray + id, A, D, M);
+                    long long gid;
+                    if (A.nseg > 0) {
+                        gid = segment_ray(A, id);
+                    } else {
+                        if (A.order) id = (long long)A.order[id];
+                        gid = A.first_ray + id;
+                    }
+                    active = ray_init<KIND>(R, gid, A, D, M);
                     if (!active) done = R.job;
                 }
                 if (A.remaining) count_done(A, done);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtartarus.so")
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_TOO_LARGE, E_NOT_FOUND, E_AGAIN = 0, -1, -2, -3, -4, -5, -6
 ESCAPED, CAPTURED, FAILED, ON_DISK = 0, 1, 2, 3
 SHADE_OBSERVED, SHADE_INTRINSIC = 0, 1
+SERVE_SMALLEST_FIRST, SERVE_ARRIVAL = 0, 1
 METRIC_KERR, METRIC_TABLE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 ORDER_DEFAULT, ORDER_PIXEL, ORDER_COST, ORDER_TILE = 0, 1, 2, 3
@@ -91,6 +92,7 @@ def lib():
         L.tartarus_submit.argtypes = [P(Metric), P(Camera), P(Disk), P(Solver), P(Outputs), P(C.c_uint64)]
         L.tartarus_poll.argtypes = [C.c_uint64, P(C.c_int)]
         L.tartarus_wait.argtypes = [C.c_uint64, C.c_int64]
+        L.tartarus_serving_order.argtypes = [C.c_int]
         L.tartarus_cancel.argtypes = [C.c_uint64]
         L.tartarus_ticket_times.argtypes = [C.c_uint64, P(C.c_int64)]
         L.tartarus_last_error.restype = C.c_char_p
@@ -207,6 +209,10 @@ def tartarus_build_kerr_table(a: float, nr: int, nth: int, r_min: float, r_max: 
     assert table.dtype == torch.float64 and table.is_cuda and table.numel() == nr * nth * 20
     _check(lib().tartarus_build_kerr_table(a, nr, nth, r_min, r_max, C.c_void_p(table.data_ptr()),
                                            _stream(stream)))
+
+
+def tartarus_serving_order(order: int) -> None:
+    _check(lib().tartarus_serving_order(int(order)))
 
 
 def tartarus_submit(metric: Metric, cam: Camera, disk: Disk, solver: Solver, outputs: dict) -> int:

@@ -126,6 +126,8 @@ def test_calls_before_init_fail_cleanly(T):
     assert T.lib().tartarus_poll(C.c_uint64(12345), C.byref(st)) == T.E_NOT_FOUND
     t = C.c_uint64(0)
     assert T.lib().tartarus_submit(C.byref(m), C.byref(c), C.byref(d), C.byref(s), C.byref(so), C.byref(t)) == T.E_DEVICE
+    assert T.lib().tartarus_serving_order(T.SERVE_ARRIVAL) == T.E_DEVICE
+    assert T.lib().tartarus_serving_order(7) == T.E_INVALID
 
 
 def test_null_outputs_rejected(T):

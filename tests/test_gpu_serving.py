@@ -147,6 +147,27 @@ def test_other_methods_and_disk_variants_served(T, method):
             assert np.all(g["n_hits"] <= 1)
 
 
+@pytest.mark.parametrize("order", [0, 1], ids=["smallest_first", "arrival"])
+def test_serving_orders_give_the_same_bits(T, order):
+    """Both hand-out orders of the serving queue: every request of a mixed
+    stream equals tracing it alone."""
+    T.tartarus_serving_order(order)
+    reqs = stream_requests(6, seed=40, res=(16, 48, 96))
+    mk = lambda r: (T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
+                    T.make_solver(r["solver"]))
+    outs = [T.alloc_outputs(r["camera"]["nx"] * r["camera"]["ny"]) for r in reqs]
+    ts = [T.tartarus_submit(*mk(r), o) for r, o in zip(reqs, outs)]
+    for t in ts:
+        T.tartarus_wait(t, 60000)
+    for r, o in zip(reqs, outs):
+        ref = alone(T, r, 0)
+        g = T.to_numpy(o)
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (order, r["id"], k)
+    with pytest.raises(T.TartarusError):
+        T.tartarus_serving_order(5)
+
+
 def test_request_larger_than_the_lane_count(T):
     """More rays than device lanes: lanes refill in partial waves and park at
     epoch ends; every ray id handed out must be traced (no request may stall)."""
