@@ -264,8 +264,9 @@ int tartarus_build_kerr_table(double a, int nr, int nth, double r_min, double r_
 
 /* Hand-out order of the serving queue's unstarted rays, applied from the next
  * epoch on: TARTARUS_SERVE_SMALLEST_FIRST (default) gives lanes to the rays of
- * the admitted request with the fewest rays first, so small images finish
- * within a few epochs of their arrival while large ones run behind them;
+ * the admitted request with the fewest rays not yet handed out first, so small
+ * images finish within a few epochs of their arrival while large ones run
+ * behind them;
  * TARTARUS_SERVE_ARRIVAL hands them out in admission order.  Rays already on
  * a lane always run to their end, and results do not depend on the order.
  * E_INVALID for another value, E_DEVICE before tartarus_init. */

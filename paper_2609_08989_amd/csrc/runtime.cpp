@@ -938,15 +938,15 @@ int server_round(std::unique_lock<std::mutex>& lk)
     }
     if (nd == 0) return TARTARUS_OK;
     // ---- this epoch's queue: the unstarted rays of every live request, one
-    // segment each, smallest request first (or in arrival order); cancelled
-    // requests go first so that their rays drain at once
+    // segment each, fewest unstarted rays first (or in arrival order);
+    // cancelled requests go first so that their rays drain at once
     std::vector<std::tuple<int, long long, long long, int>> segs;   // (class, key, ray_begin, entry)
     for (int e = 0; e < kMaxEntries; ++e) {
         const uint64_t t = S.entry_ticket[e];
         if (!t) continue;
         const Request& R = S.reqs[t];
         if (R.started >= R.nrays) continue;
-        const long long key = S.serve_order == TARTARUS_SERVE_SMALLEST_FIRST ? R.nrays : R.ray_begin;
+        const long long key = S.serve_order == TARTARUS_SERVE_SMALLEST_FIRST ? R.nrays - R.started : R.ray_begin;
         segs.push_back({S.hjobs[e].cancelled ? 0 : 1, key, R.ray_begin, e});
     }
     std::sort(segs.begin(), segs.end());
