@@ -202,7 +202,7 @@ enum { TARTARUS_ORDER_DEFAULT = 0, TARTARUS_ORDER_PIXEL = 1, TARTARUS_ORDER_COST
 
 typedef struct {
     int block_threads;     /* 64, 128 or 256                                        */
-    int blocks_per_cu;     /* resident workgroups per compute unit                  */
+    int blocks_per_cu;     /* resident workgroups per compute unit; default: 1 when the trace has fewer than 8 rays per lane of one block per CU, else the occupancy maximum */
     int chunk;             /* least ray ids a wavefront takes per fetch; ids beyond its idle lanes wait in it (1 = none wait) */
     int refill_min;        /* idle lanes that trigger a refill (1..64)              */
     int order;             /* TARTARUS_ORDER_*                                      */

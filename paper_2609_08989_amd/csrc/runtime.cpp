@@ -319,7 +319,16 @@ tartarus_launch default_launch(int kind, int prec, int method)
     return L;
 }
 
-int resolve_launch(int kind, int prec, int method, const tartarus_launch* req_in, tartarus_launch& L, int& grid)
+// Resolve a launch request against the tuned or default shape.  n_rays > 0
+// (a one-shot trace of that many rays) lets an unset blocks_per_cu depend on
+// the size: with few rays per lane the longest rays set the kernel time and a
+// lone wavefront per SIMD runs them fastest; with many, a second wavefront's
+// throughput wins (measured: one block of 256 per CU on a 512^2 image, two on
+// 1024^2 and 2048^2 images).
+constexpr long long kRaysPerLaneForFullOccupancy = 8;
+
+int resolve_launch(int kind, int prec, int method, const tartarus_launch* req_in, tartarus_launch& L, int& grid,
+                   long long n_rays = 0)
 {
     // req_in may point at L itself: read the request before L is overwritten
     tartarus_launch req_copy;
@@ -344,6 +353,9 @@ int resolve_launch(int kind, int prec, int method, const tartarus_launch* req_in
     int occ = 0;
     HIP_TRY(tartarus_occupancy(kind, prec, method, L.block_threads, &occ));
     if (occ < 1) return fail(TARTARUS_E_DEVICE, "kernel cannot be resident with this block size");
+    if (L.blocks_per_cu <= 0 && n_rays > 0 &&
+        n_rays < kRaysPerLaneForFullOccupancy * (long long)g_dev.cus * L.block_threads)
+        L.blocks_per_cu = 1;
     if (L.blocks_per_cu <= 0 || L.blocks_per_cu > occ) L.blocks_per_cu = occ;
     grid = g_dev.cus * L.blocks_per_cu;
     return TARTARUS_OK;
@@ -357,7 +369,8 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
     const int kind = metric->kind, prec = solver->precision, method = solver->method;
     tartarus_launch L;
     int grid = 0;
-    int rc = resolve_launch(kind, prec, method, launch, L, grid);
+    const long long n_rays = (long long)cams[0].nx * cams[0].ny * ncams;
+    int rc = resolve_launch(kind, prec, method, launch, L, grid, n_rays);
     if (rc) return rc;
     Slot* S = nullptr;
     if ((rc = take_slot(ncams, S))) return rc;
