@@ -228,7 +228,8 @@ int tartarus_validate(const tartarus_metric* metric, const tartarus_camera* cams
 /* Trace every pixel of ncams cameras (all with the same nx, ny) into outputs,
  * asynchronously on hip_stream (a hipStream_t; NULL = the null stream).  The
  * call enqueues the work and returns; results are valid once the stream has
- * completed.  Buffers must stay alive until then. */
+ * completed.  Buffers must stay alive until then.  Not for HIP graph capture:
+ * the job table is staged in pinned slots that later calls reuse. */
 int tartarus_trace(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
                    const tartarus_disk* disk, const tartarus_solver* solver,
                    const tartarus_outputs* out, void* hip_stream);
