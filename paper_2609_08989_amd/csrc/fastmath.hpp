@@ -13,6 +13,7 @@
 #pragma once
 
 #include <cmath>
+#include <cstring>
 
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
@@ -27,6 +28,17 @@ constexpr double kPio2Hi = 1.5707963267948966;       // pi/2 = hi + mid + lo
 constexpr double kPio2Mid = 6.123233995736766e-17;
 constexpr double kPio2Lo = -1.4973849048591698e-33;
 constexpr double kTwoOverPi = 0.6366197723675814;
+
+// x with its sign bit XORed with bit 31 of hi_bit (the other bits of hi_bit
+// must be zero).
+TT_HD inline double flip_sign(double x, unsigned hi_bit)
+{
+    unsigned long long u;
+    std::memcpy(&u, &x, sizeof u);
+    u ^= (unsigned long long)hi_bit << 32;
+    std::memcpy(&x, &u, sizeof u);
+    return x;
+}
 
 TT_HD inline void sincos64(double x, double* sp, double* cp)
 {
@@ -52,11 +64,14 @@ TT_HD inline void sincos64(double x, double* sp, double* cp)
     pc = std::fma(pc, r2, 0.041666666666666449);
     pc = std::fma(pc, r2, -0.5);
     const double cr = std::fma(pc, r2, 1.0);
-    const int q = ((int)(long long)k) & 3;
+    // quadrant: |k| < 2^20, so the int conversion is exact (one instruction,
+    // where a 64-bit integer conversion of a double takes four); the signs are
+    // applied by flipping the sign bit (same bits as negation)
+    const int q = ((int)k) & 3;
     const double s = (q & 1) ? cr : sr;
     const double c = (q & 1) ? sr : cr;
-    *sp = (q & 2) ? -s : s;
-    *cp = ((q + 1) & 2) ? -c : c;
+    *sp = flip_sign(s, (unsigned)(q & 2) << 30);
+    *cp = flip_sign(c, (unsigned)((q + 1) & 2) << 30);
 }
 
 // sincos32: the single-precision counterpart for the FP32 far-field stages.

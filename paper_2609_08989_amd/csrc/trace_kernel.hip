@@ -602,6 +602,22 @@ __device__ __forceinline__ void stages32(const Ray& R, double h, Deriv<double>& 
 
 // One attempted DP45 step with FP64 stages.  Writes the fifth-order state y5
 // (dynamic components), k7 = f(y5), H(y5), cos(theta5) and the error vector.
+// The FP64 DP45 coefficients in constant memory, read with scalar loads one
+// stage's worth at a time.  FP64 VALU instructions cannot encode a 64-bit
+// literal, so written as immediates every coefficient costs two s_mov per
+// attempt; held across the loop they exceed the SGPR file and spill.  A
+// constant-memory pointer passed through an empty asm cannot be hoisted out of
+// the integration loop, so each stage's loads stay next to their use
+// (measured: 2 % off the 512 x 512, a = 0.9 trace at rtol 3e-10 with one
+// wavefront per SIMD).
+typedef const __attribute__((address_space(4))) double ConstDouble;
+__constant__ double kDp45Coef[26] = {A21, A31, A32, A41, A42, A43, A51, A52, A53, A54, A61, A62, A63, A64, A65,
+                                     B1, B3, B4, B5, B6, E1, E3, E4, E5, E6, E7};
+__device__ __forceinline__ ConstDouble* opaque_const(ConstDouble* p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
 template <int KIND>
 __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
                                          Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
@@ -610,31 +626,59 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
     const double a = R.a;
     Deriv<double> k2, k3, k4, k5, k6;
     double Hd, cd;
-    M.rhs(a, fma(h, A21 * k1.r, R.r), fma(h, A21 * k1.th, R.th), fma(h, A21 * k1.pr, R.pr),
-          fma(h, A21 * k1.pth, R.pth), R.pt, R.pph, k2, Hd, cd);
+    ConstDouble* K = opaque_const((ConstDouble*)kDp45Coef);
+    {
+        const double A21 = K[0];
+        M.rhs(a, fma(h, A21 * k1.r, R.r), fma(h, A21 * k1.th, R.th), fma(h, A21 * k1.pr, R.pr),
+              fma(h, A21 * k1.pth, R.pth), R.pt, R.pph, k2, Hd, cd);
+    }
+    K = opaque_const(K);
+    {
+        const double A31 = K[1], A32 = K[2];
 #define TT_S3(c) fma(h, fma(A32, k2.c, A31 * k1.c), R.c)
-    M.rhs(a, TT_S3(r), TT_S3(th), TT_S3(pr), TT_S3(pth), R.pt, R.pph, k3, Hd, cd);
+        M.rhs(a, TT_S3(r), TT_S3(th), TT_S3(pr), TT_S3(pth), R.pt, R.pph, k3, Hd, cd);
+    }
+    K = opaque_const(K);
+    {
+        const double A41 = K[3], A42 = K[4], A43 = K[5];
 #define TT_S4(c) fma(h, fma(A43, k3.c, fma(A42, k2.c, A41 * k1.c)), R.c)
-    M.rhs(a, TT_S4(r), TT_S4(th), TT_S4(pr), TT_S4(pth), R.pt, R.pph, k4, Hd, cd);
+        M.rhs(a, TT_S4(r), TT_S4(th), TT_S4(pr), TT_S4(pth), R.pt, R.pph, k4, Hd, cd);
+    }
+    K = opaque_const(K);
+    {
+        const double A51 = K[6], A52 = K[7], A53 = K[8], A54 = K[9];
 #define TT_S5(c) fma(h, fma(A54, k4.c, fma(A53, k3.c, fma(A52, k2.c, A51 * k1.c))), R.c)
-    M.rhs(a, TT_S5(r), TT_S5(th), TT_S5(pr), TT_S5(pth), R.pt, R.pph, k5, Hd, cd);
+        M.rhs(a, TT_S5(r), TT_S5(th), TT_S5(pr), TT_S5(pth), R.pt, R.pph, k5, Hd, cd);
+    }
+    K = opaque_const(K);
+    {
+        const double A61 = K[10], A62 = K[11], A63 = K[12], A64 = K[13], A65 = K[14];
 #define TT_S6(c) fma(h, fma(A65, k5.c, fma(A64, k4.c, fma(A63, k3.c, fma(A62, k2.c, A61 * k1.c)))), R.c)
-    M.rhs(a, TT_S6(r), TT_S6(th), TT_S6(pr), TT_S6(pth), R.pt, R.pph, k6, Hd, cd);
+        M.rhs(a, TT_S6(r), TT_S6(th), TT_S6(pr), TT_S6(pth), R.pt, R.pph, k6, Hd, cd);
+    }
+    K = opaque_const(K);
+    {
+        const double B1 = K[15], B3 = K[16], B4 = K[17], B5 = K[18], B6 = K[19];
 #define TT_Y5(c) fma(h, fma(B6, k6.c, fma(B5, k5.c, fma(B4, k4.c, fma(B3, k3.c, B1 * k1.c)))), R.c)
-    y5.t = TT_Y5(t);
-    y5.r = TT_Y5(r);
-    y5.th = TT_Y5(th);
-    y5.ph = TT_Y5(ph);
-    y5.pr = TT_Y5(pr);
-    y5.pth = TT_Y5(pth);
+        y5.t = TT_Y5(t);
+        y5.r = TT_Y5(r);
+        y5.th = TT_Y5(th);
+        y5.ph = TT_Y5(ph);
+        y5.pr = TT_Y5(pr);
+        y5.pth = TT_Y5(pth);
+    }
     M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+    K = opaque_const(K);
+    {
+        const double E1 = K[20], E3 = K[21], E4 = K[22], E5 = K[23], E6 = K[24], E7 = K[25];
 #define TT_E(c) h * fma(E7, k7.c, fma(E6, k6.c, fma(E5, k5.c, fma(E4, k4.c, fma(E3, k3.c, E1 * k1.c)))))
-    e.t = TT_E(t);
-    e.r = TT_E(r);
-    e.th = TT_E(th);
-    e.ph = TT_E(ph);
-    e.pr = TT_E(pr);
-    e.pth = TT_E(pth);
+        e.t = TT_E(t);
+        e.r = TT_E(r);
+        e.th = TT_E(th);
+        e.ph = TT_E(ph);
+        e.pr = TT_E(pr);
+        e.pth = TT_E(pth);
+    }
 #undef TT_S3
 #undef TT_S4
 #undef TT_S5
