@@ -24,10 +24,20 @@
 
 namespace tartarus {
 
-constexpr double kPio2Hi = 1.5707963267948966;       // pi/2 = hi + mid + lo
-constexpr double kPio2Mid = 6.123233995736766e-17;
-constexpr double kPio2Lo = -1.4973849048591698e-33;
-constexpr double kTwoOverPi = 0.6366197723675814;
+// Coefficients of sincos64 in the order it uses them: 2/pi; pi/2 = hi + mid +
+// lo; the sine polynomial s6 .. s1 and the cosine polynomial c7 .. c2 (Horner
+// order; cos r = 1 + r^2 (c1 + ...) with c1 = -1/2 exact).
+constexpr double kSinCos64[16] = {
+    0.6366197723675814,   1.5707963267948966,    6.123233995736766e-17,  -1.4973849048591698e-33,
+    1.5894740706160615e-10, -2.5050717053109253e-08, 2.7557313376976021e-06, -0.0001984126982865223,
+    0.0083333333333203662, -0.16666666666666616,
+    -1.1353381481384318e-11, 2.0875582423297387e-09, -2.7557313098175798e-07, 2.4801587283882876e-05,
+    -0.0013888888888861099, 0.041666666666666449};
+
+// The coefficients as compile-time immediates.
+struct SinCosImm {
+    TT_HD double operator()(int i) const { return kSinCos64[i]; }
+};
 
 // x with its sign bit XORed with bit 31 of hi_bit (the other bits of hi_bit
 // must be zero).
@@ -40,28 +50,24 @@ TT_HD inline double flip_sign(double x, unsigned hi_bit)
     return x;
 }
 
-TT_HD inline void sincos64(double x, double* sp, double* cp)
+// sincos64 with the coefficients taken from coef(i) (i indexes kSinCos64).
+template <class Coef>
+TT_HD inline void sincos64_with(double x, double* sp, double* cp, Coef coef)
 {
-    const double k = std::rint(x * kTwoOverPi);
-    double r = std::fma(-k, kPio2Hi, x);
-    r = std::fma(-k, kPio2Mid, r);
-    r = std::fma(-k, kPio2Lo, r);
+    const double k = std::rint(x * coef(0));
+    double r = std::fma(-k, coef(1), x);
+    r = std::fma(-k, coef(2), r);
+    r = std::fma(-k, coef(3), r);
     const double r2 = r * r;
     // sin r = r + r^3 (s1 + r^2 (s2 + ... + r^2 s6))
-    double ps = 1.5894740706160615e-10;
-    ps = std::fma(ps, r2, -2.5050717053109253e-08);
-    ps = std::fma(ps, r2, 2.7557313376976021e-06);
-    ps = std::fma(ps, r2, -0.0001984126982865223);
-    ps = std::fma(ps, r2, 0.0083333333333203662);
-    ps = std::fma(ps, r2, -0.16666666666666616);
+    double ps = coef(4);
+#pragma unroll
+    for (int i = 5; i <= 9; ++i) ps = std::fma(ps, r2, coef(i));
     const double sr = std::fma(ps * r2, r, r);
     // cos r = 1 + r^2 (c1 + r^2 (c2 + ... + r^2 c7))
-    double pc = -1.1353381481384318e-11;
-    pc = std::fma(pc, r2, 2.0875582423297387e-09);
-    pc = std::fma(pc, r2, -2.7557313098175798e-07);
-    pc = std::fma(pc, r2, 2.4801587283882876e-05);
-    pc = std::fma(pc, r2, -0.0013888888888861099);
-    pc = std::fma(pc, r2, 0.041666666666666449);
+    double pc = coef(10);
+#pragma unroll
+    for (int i = 11; i <= 15; ++i) pc = std::fma(pc, r2, coef(i));
     pc = std::fma(pc, r2, -0.5);
     const double cr = std::fma(pc, r2, 1.0);
     // quadrant: |k| < 2^20, so the int conversion is exact (one instruction,
@@ -72,6 +78,11 @@ TT_HD inline void sincos64(double x, double* sp, double* cp)
     const double c = (q & 1) ? sr : cr;
     *sp = flip_sign(s, (unsigned)(q & 2) << 30);
     *cp = flip_sign(c, (unsigned)((q + 1) & 2) << 30);
+}
+
+TT_HD inline void sincos64(double x, double* sp, double* cp)
+{
+    sincos64_with(x, sp, cp, SinCosImm{});
 }
 
 // sincos32: the single-precision counterpart for the FP32 far-field stages.

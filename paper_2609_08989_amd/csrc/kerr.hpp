@@ -24,11 +24,13 @@ struct Deriv {
 };
 
 // FP64 right-hand side.  Also returns H (Eq. (1)) and cos(theta) of the point.
+// coef supplies the sincos64 coefficients (compile-time immediates by default).
+template <class Coef = SinCosImm>
 __device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double pr, double pth, double pt,
-                                           double pph, Deriv<double>& d, double& H, double& cth)
+                                           double pph, Deriv<double>& d, double& H, double& cth, Coef coef = {})
 {
     double s, c;
-    sincos64(th, &s, &c);
+    sincos64_with(th, &s, &c, coef);
     const double a2 = a * a;
     const double r2 = r * r;
     const double s2 = s * s;

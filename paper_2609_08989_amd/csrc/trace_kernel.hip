@@ -126,11 +126,14 @@ struct Ray {
 template <int KIND>
 struct MetricOps {
     TableView T;
+    // coef: where the analytic right-hand side takes its sine/cosine
+    // coefficients from (immediates unless a stage loop passes SinCosLoad)
+    template <class Coef = SinCosImm>
     __device__ __forceinline__ void rhs(double a, double r, double th, double pr, double pth, double pt, double pph,
-                                        Deriv<double>& d, double& H, double& c) const
+                                        Deriv<double>& d, double& H, double& c, Coef coef = {}) const
     {
         if (KIND == 0)
-            kerr_rhs64(a, r, th, pr, pth, pt, pph, d, H, c);
+            kerr_rhs64(a, r, th, pr, pth, pt, pph, d, H, c, coef);
         else
             table_rhs64(T, r, th, pr, pth, pt, pph, d, H, c);
     }
@@ -618,6 +621,18 @@ __device__ __forceinline__ ConstDouble* opaque_const(ConstDouble* p)
     asm volatile("" : "+s"(p));
     return p;
 }
+
+// The sincos64 coefficients in constant memory: the stage loop reads them once
+// per attempt (two scalar loads) through an opaque pointer, and all six
+// right-hand sides of the attempt share the loaded values.
+__constant__ double kSinCos64Const[16] = {kSinCos64[0],  kSinCos64[1],  kSinCos64[2],  kSinCos64[3],
+                                          kSinCos64[4],  kSinCos64[5],  kSinCos64[6],  kSinCos64[7],
+                                          kSinCos64[8],  kSinCos64[9],  kSinCos64[10], kSinCos64[11],
+                                          kSinCos64[12], kSinCos64[13], kSinCos64[14], kSinCos64[15]};
+struct SinCosLoad {
+    ConstDouble* p;
+    __device__ double operator()(int i) const { return p[i]; }
+};
 template <int KIND>
 __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
                                          Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
@@ -626,35 +641,36 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
     const double a = R.a;
     Deriv<double> k2, k3, k4, k5, k6;
     double Hd, cd;
+    const SinCosLoad sc{opaque_const((ConstDouble*)kSinCos64Const)};
     ConstDouble* K = opaque_const((ConstDouble*)kDp45Coef);
     {
         const double A21 = K[0];
         M.rhs(a, fma(h, A21 * k1.r, R.r), fma(h, A21 * k1.th, R.th), fma(h, A21 * k1.pr, R.pr),
-              fma(h, A21 * k1.pth, R.pth), R.pt, R.pph, k2, Hd, cd);
+              fma(h, A21 * k1.pth, R.pth), R.pt, R.pph, k2, Hd, cd, sc);
     }
     K = opaque_const(K);
     {
         const double A31 = K[1], A32 = K[2];
 #define TT_S3(c) fma(h, fma(A32, k2.c, A31 * k1.c), R.c)
-        M.rhs(a, TT_S3(r), TT_S3(th), TT_S3(pr), TT_S3(pth), R.pt, R.pph, k3, Hd, cd);
+        M.rhs(a, TT_S3(r), TT_S3(th), TT_S3(pr), TT_S3(pth), R.pt, R.pph, k3, Hd, cd, sc);
     }
     K = opaque_const(K);
     {
         const double A41 = K[3], A42 = K[4], A43 = K[5];
 #define TT_S4(c) fma(h, fma(A43, k3.c, fma(A42, k2.c, A41 * k1.c)), R.c)
-        M.rhs(a, TT_S4(r), TT_S4(th), TT_S4(pr), TT_S4(pth), R.pt, R.pph, k4, Hd, cd);
+        M.rhs(a, TT_S4(r), TT_S4(th), TT_S4(pr), TT_S4(pth), R.pt, R.pph, k4, Hd, cd, sc);
     }
     K = opaque_const(K);
     {
         const double A51 = K[6], A52 = K[7], A53 = K[8], A54 = K[9];
 #define TT_S5(c) fma(h, fma(A54, k4.c, fma(A53, k3.c, fma(A52, k2.c, A51 * k1.c))), R.c)
-        M.rhs(a, TT_S5(r), TT_S5(th), TT_S5(pr), TT_S5(pth), R.pt, R.pph, k5, Hd, cd);
+        M.rhs(a, TT_S5(r), TT_S5(th), TT_S5(pr), TT_S5(pth), R.pt, R.pph, k5, Hd, cd, sc);
     }
     K = opaque_const(K);
     {
         const double A61 = K[10], A62 = K[11], A63 = K[12], A64 = K[13], A65 = K[14];
 #define TT_S6(c) fma(h, fma(A65, k5.c, fma(A64, k4.c, fma(A63, k3.c, fma(A62, k2.c, A61 * k1.c)))), R.c)
-        M.rhs(a, TT_S6(r), TT_S6(th), TT_S6(pr), TT_S6(pth), R.pt, R.pph, k6, Hd, cd);
+        M.rhs(a, TT_S6(r), TT_S6(th), TT_S6(pr), TT_S6(pth), R.pt, R.pph, k6, Hd, cd, sc);
     }
     K = opaque_const(K);
     {
@@ -667,7 +683,7 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
         y5.pr = TT_Y5(pr);
         y5.pth = TT_Y5(pth);
     }
-    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, sc);
     K = opaque_const(K);
     {
         const double E1 = K[20], E3 = K[21], E4 = K[22], E5 = K[23], E6 = K[24], E7 = K[25];
