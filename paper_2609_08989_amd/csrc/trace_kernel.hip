@@ -918,41 +918,50 @@ __device__ __forceinline__ bool stages_verlet(const Ray& R, const MetricOps<KIND
 
 __device__ __forceinline__ double sq_ratio(double e, double y0, double y1, double atol, double rtol)
 {
-    const double z = e * rcp64(fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
+    const double z = e * rcp64_coarse(fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
     return z * z;
 }
 
-// x^(-1/P) for P = 5 or 11 on the range step_factor passes in: an FP32
-// estimate refined by two Newton steps on y^-P = x
-// (y <- y ((P + 1) - x y^P) / P), which take the ~1e-7 relative error of the
-// estimate below an ulp of the double result.
+// y^N for a compile-time N >= 1 by repeated squaring.
+template <int N>
+__device__ __forceinline__ double ipow(double y)
+{
+    if constexpr (N == 1) {
+        return y;
+    } else if constexpr (N % 2 == 0) {
+        const double h = ipow<N / 2>(y);
+        return h * h;
+    } else {
+        return ipow<N - 1>(y) * y;
+    }
+}
+
+// x^(-1/P) on the range step_factor passes in: an FP32 estimate refined by
+// two Newton steps on y^-P = x (y <- y ((P + 1) - x y^P) / P), which take the
+// ~1e-7 relative error of the estimate below an ulp of the double result.
 template <int P>
 __device__ __forceinline__ double pow_m_inv(double x)
 {
-    static_assert(P == 5 || P == 11, "exponent");
     double y = (double)exp2f(log2f((float)x) * (-1.0f / (float)P));
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double y2 = y * y;
-        const double y4 = y2 * y2;
-        const double yp = P == 5 ? y4 * y : y4 * y4 * y2 * y;
-        y = y * fma(-x, yp, (double)(P + 1)) * (1.0 / (double)P);
-    }
+    for (int i = 0; i < 2; ++i) y = y * fma(-x, ipow<P>(y), (double)(P + 1)) * (1.0 / (double)P);
     return y;
 }
 
-// Step-size factor of the elementary controller:
-// min(fmx, max(0.2, 0.9 err^(-1/P))), P = 5 for the 5(4) pairs and 2K - 1 for
-// the extrapolation.  Below lo and above hi the clamps decide the result
-// without the power (0.9 lo^(-1/P) >= 10 and 0.9 hi^(-1/P) <= 0.2).
+// Step-size factor of the elementary controller from the squared error norm
+// err2 = err^2: min(fmx, max(0.2, 0.9 err^(-1/P))) = min(fmx, max(0.2,
+// 0.9 err2^(-1/(2P)))), P = 5 for the 5(4) pairs and 2K - 1 for the
+// extrapolation (working on err^2 saves the square root).  Below lo^2 and
+// above hi^2 the clamps decide the result without the power
+// (0.9 lo^(-1/P) >= 10 and 0.9 hi^(-1/P) <= 0.2).
 template <int P>
-__device__ __forceinline__ double step_factor(double err, double fmx)
+__device__ __forceinline__ double step_factor(double err2, double fmx)
 {
     constexpr double lo = P == 5 ? 1e-6 : 1e-12;
     constexpr double hi = P == 5 ? 1e5 : 1e8;
-    if (err < lo) return fmx;
-    if (err > hi) return 0.2;
-    return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<P>(err)));
+    if (err2 < lo * lo) return fmx;
+    if (err2 > hi * hi) return 0.2;
+    return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<2 * P>(err2)));
 }
 
 // One attempt; returns true when the ray has terminated (outputs written).
@@ -1001,12 +1010,12 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
         acc += sq_ratio(e.pr, R.pr, y5.pr, atol, rtol);
         acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
         // p_t and p_phi have zero error (their derivatives vanish identically)
-        const double err = sqrt(acc * 0.125);
+        const double err2 = acc * 0.125;   // squared RMS error over the 8 components
         // elementary controller, evaluated once for both outcomes: after a
         // rejection (or for one) the step may not grow
-        const bool ok = err <= 1.0;
+        const bool ok = err2 <= 1.0;
         constexpr int P = METHOD == METHOD_GBS ? 2 * kGbsColumns - 1 : 5;
-        fac = isnan(err) ? 0.2 : step_factor<P>(err, (ok && !R.rej_prev) ? 10.0 : 1.0);
+        fac = isnan(err2) ? 0.2 : step_factor<P>(err2, (ok && !R.rej_prev) ? 10.0 : 1.0);
         if (!ok) {
             // rejected; a NaN or infinite error also lands here
             R.n_rej++;
