@@ -99,20 +99,23 @@ def shape(L):
 
 
 def time_leg(T, torch, args_tuple, out, steps, warmup, launch=None):
-    stream = torch.cuda.current_stream()
+    """Wall time of `steps` traces (bracketed by device synchronizations), and
+    the mean duration of their integrator launches, from the HIP event pair the
+    library records around each one on the trace's stream."""
     for _ in range(warmup):
         T.tartarus_trace(*args_tuple, out, launch=launch)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    T.tartarus_kernel_time()                 # drop anything recorded before
+    T.tartarus_kernel_timing(True)
     t0 = time.perf_counter()
-    e0.record(stream)
     for _ in range(steps):
         T.tartarus_trace(*args_tuple, out, launch=launch)
-    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall, e0.elapsed_time(e1) / steps
+    T.tartarus_kernel_timing(False)
+    kernel_total_ms, launches = T.tartarus_kernel_time()
+    assert launches == steps, (launches, steps)
+    return wall, kernel_total_ms / launches
 
 
 def cpu_baseline(w, solver, seconds: float) -> dict:

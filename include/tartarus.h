@@ -247,6 +247,20 @@ int tartarus_autotune(const tartarus_metric* metric, const tartarus_camera* cams
                       const tartarus_disk* disk, const tartarus_solver* solver,
                       const tartarus_outputs* out, void* hip_stream, tartarus_launch* best);
 
+/* Integrator timing, for benchmarks and profilers.  While it is enabled, each
+ * launch of the persistent integrator that tartarus_trace,
+ * tartarus_trace_launch or tartarus_autotune enqueue is bracketed by a pair of
+ * HIP events recorded on the trace's stream; the ordering and finishing
+ * kernels of the trace fall outside the pair, and serving epochs are not
+ * timed.  tartarus_kernel_time waits for the recorded launches, writes the sum
+ * of their durations (milliseconds) and their number, and starts both sums
+ * afresh.  Disabling stops the recording; launches recorded before stay
+ * readable.  enable: 0 or 1 (else E_INVALID); NULL outputs: E_INVALID; both
+ * return E_DEVICE before tartarus_init.  The event pairs are the library's and
+ * are reused. */
+int tartarus_kernel_timing(int enable);
+int tartarus_kernel_time(double* total_ms, long long* launches);
+
 /* Fill a caller-owned DEVICE table (layout of tartarus_metric.table, nr*nth*20
  * doubles) from the analytic Kerr metric with spin a, on hip_stream. */
 int tartarus_build_kerr_table(double a, int nr, int nth, double r_min, double r_max, double* table,

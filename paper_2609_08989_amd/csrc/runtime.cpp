@@ -102,8 +102,29 @@ struct Device {
     Slot slots[kSlots];
     int next_slot = 0;
     std::map<int, tartarus_launch> tuned;  // key: tune_key(kind, precision, method)
+    // integrator timing (tartarus_kernel_timing): an event pair around each
+    // integrator launch while on; pairs are read back by tartarus_kernel_time
+    bool ktime_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ktime_pending, ktime_spare;
 };
 Device g_dev;
+
+// Drains the recorded integrator event pairs into (total ms, launches).
+int ktime_collect(double& total_ms, long long& launches)
+{
+    total_ms = 0.0;
+    launches = 0;
+    for (auto& pr : g_dev.ktime_pending) {
+        HIP_TRY(hipEventSynchronize(pr.second));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        total_ms += ms;
+        ++launches;
+        g_dev.ktime_spare.push_back(pr);
+    }
+    g_dev.ktime_pending.clear();
+    return TARTARUS_OK;
+}
 
 int take_slot(int njobs, Slot*& out)
 {
@@ -432,7 +453,22 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
         A.order = order;
     }
     A.tile = L.order == TARTARUS_ORDER_TILE ? 1 : 0;
+    std::pair<hipEvent_t, hipEvent_t> kt(nullptr, nullptr);
+    if (g_dev.ktime_on) {
+        if (!g_dev.ktime_spare.empty()) {
+            kt = g_dev.ktime_spare.back();
+            g_dev.ktime_spare.pop_back();
+        } else {
+            HIP_TRY(hipEventCreate(&kt.first));
+            HIP_TRY(hipEventCreate(&kt.second));
+        }
+        HIP_TRY(hipEventRecord(kt.first, stream));
+    }
     HIP_TRY(tartarus_launch_trace(kind, prec, method, &A, grid, L.block_threads, stream));
+    if (kt.first) {
+        HIP_TRY(hipEventRecord(kt.second, stream));
+        g_dev.ktime_pending.push_back(kt);
+    }
     for (int c0 = 0; c0 < ncams; c0 += 65535)
         HIP_TRY(tartarus_launch_finish(&A, c0, std::min(65535, ncams - c0), per, stream));
     HIP_TRY(hipEventRecord(S->ev, stream));
@@ -647,8 +683,35 @@ extern "C" int tartarus_shutdown(void)
         S = Slot();
     }
     g_dev.tuned.clear();
+    for (auto* v : {&g_dev.ktime_pending, &g_dev.ktime_spare}) {
+        for (auto& pr : *v) {
+            (void)hipEventSynchronize(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        v->clear();
+    }
+    g_dev.ktime_on = false;
     g_dev.ready = false;
     return TARTARUS_OK;
+}
+
+extern "C" int tartarus_kernel_timing(int enable)
+{
+    if (enable != 0 && enable != 1) return fail(TARTARUS_E_INVALID, "enable must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    g_dev.ktime_on = enable == 1;
+    return TARTARUS_OK;
+}
+
+extern "C" int tartarus_kernel_time(double* total_ms, long long* launches)
+{
+    if (!total_ms || !launches) return fail(TARTARUS_E_INVALID, "total_ms and launches must not be NULL");
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    HIP_TRY(hipSetDevice(g_dev.id));
+    return ktime_collect(*total_ms, *launches);
 }
 
 // ---------------------------------------------------------------------------

@@ -93,6 +93,8 @@ def lib():
         L.tartarus_poll.argtypes = [C.c_uint64, P(C.c_int)]
         L.tartarus_wait.argtypes = [C.c_uint64, C.c_int64]
         L.tartarus_serving_order.argtypes = [C.c_int]
+        L.tartarus_kernel_timing.argtypes = [C.c_int]
+        L.tartarus_kernel_time.argtypes = [P(C.c_double), P(C.c_longlong)]
         L.tartarus_cancel.argtypes = [C.c_uint64]
         L.tartarus_ticket_times.argtypes = [C.c_uint64, P(C.c_int64)]
         L.tartarus_last_error.restype = C.c_char_p
@@ -213,6 +215,18 @@ def tartarus_build_kerr_table(a: float, nr: int, nth: int, r_min: float, r_max: 
 
 def tartarus_serving_order(order: int) -> None:
     _check(lib().tartarus_serving_order(int(order)))
+
+
+def tartarus_kernel_timing(enable: bool) -> None:
+    _check(lib().tartarus_kernel_timing(1 if enable else 0))
+
+
+def tartarus_kernel_time() -> tuple:
+    """(total milliseconds, launches) of the integrator launches timed since
+    the last call."""
+    ms, n = C.c_double(0.0), C.c_longlong(0)
+    _check(lib().tartarus_kernel_time(C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def tartarus_submit(metric: Metric, cam: Camera, disk: Disk, solver: Solver, outputs: dict) -> int:

@@ -128,6 +128,11 @@ def test_calls_before_init_fail_cleanly(T):
     assert T.lib().tartarus_submit(C.byref(m), C.byref(c), C.byref(d), C.byref(s), C.byref(so), C.byref(t)) == T.E_DEVICE
     assert T.lib().tartarus_serving_order(T.SERVE_ARRIVAL) == T.E_DEVICE
     assert T.lib().tartarus_serving_order(7) == T.E_INVALID
+    assert T.lib().tartarus_kernel_timing(1) == T.E_DEVICE
+    assert T.lib().tartarus_kernel_timing(2) == T.E_INVALID
+    ms, n = C.c_double(0.0), C.c_longlong(0)
+    assert T.lib().tartarus_kernel_time(C.byref(ms), C.byref(n)) == T.E_DEVICE
+    assert T.lib().tartarus_kernel_time(None, C.byref(n)) == T.E_INVALID
 
 
 def test_null_outputs_rejected(T):

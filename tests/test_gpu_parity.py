@@ -410,6 +410,36 @@ def test_autotune_picks_a_valid_shape_with_identical_results(T):
         assert np.array_equal(ref[k], tuned_out[k]), k
         assert np.array_equal(ref[k], again[k]), k
 
+def test_integrator_timing_counts_the_integrator_launches(T):
+    """Event timing of the integrator: one event pair per trace while enabled,
+    none while disabled; the integrator launches take part of the time of the
+    traces they belong to (ordering and finishing kernels are outside)."""
+    import torch
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=128, ny=96)
+    args = (T.make_metric(w["a"]), [T.make_camera(cam)], T.make_disk(w["disk"]), T.make_solver(w["solver"]))
+    out = T.alloc_outputs(cam["nx"] * cam["ny"])
+    T.tartarus_trace(*args, out)
+    torch.cuda.synchronize()
+    T.tartarus_kernel_time()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    T.tartarus_kernel_timing(True)
+    e0.record(st)
+    for _ in range(3):
+        T.tartarus_trace(*args, out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    T.tartarus_kernel_timing(False)
+    ms, n = T.tartarus_kernel_time()
+    say("integrator ms", ms, "launches", n, "traces ms", e0.elapsed_time(e1))
+    assert n == 3
+    assert 0.0 < ms <= e0.elapsed_time(e1) + 0.05
+    T.tartarus_trace(*args, out)
+    torch.cuda.synchronize()
+    assert T.tartarus_kernel_time() == (0.0, 0)
+
+
 # ------------------------------------------------------------------ tabulated metric
 def test_table_build_matches_oracle(T, orc):
     import torch
