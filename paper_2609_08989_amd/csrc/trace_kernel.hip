@@ -612,15 +612,30 @@ __device__ __forceinline__ void stages32(const Ray& R, double h, Deriv<double>& 
 // constant-memory pointer passed through an empty asm cannot be hoisted out of
 // the integration loop, so each stage's loads stay next to their use
 // (measured: 2 % off the 512 x 512, a = 0.9 trace at rtol 3e-10 with one
-// wavefront per SIMD).
+// wavefront per SIMD).  The tabulated metric keeps immediates: its cell
+// gather already fills the SGPR file, and the loads made it spill more.
 typedef const __attribute__((address_space(4))) double ConstDouble;
+constexpr double kDp45[26] = {A21, A31, A32, A41, A42, A43, A51, A52, A53, A54, A61, A62, A63, A64, A65,
+                              B1,  B3,  B4,  B5,  B6,  E1,  E3,  E4,  E5,  E6,  E7};
 __constant__ double kDp45Coef[26] = {A21, A31, A32, A41, A42, A43, A51, A52, A53, A54, A61, A62, A63, A64, A65,
-                                     B1, B3, B4, B5, B6, E1, E3, E4, E5, E6, E7};
+                                     B1,  B3,  B4,  B5,  B6,  E1,  E3,  E4,  E5,  E6,  E7};
 __device__ __forceinline__ ConstDouble* opaque_const(ConstDouble* p)
 {
     asm volatile("" : "+s"(p));
     return p;
 }
+
+// Where stages64 takes the coefficients from: scalar loads (LOAD) or
+// immediates.  next() starts a new stage's group of loads.
+template <bool LOAD>
+struct Dp45Source {
+    ConstDouble* p = (ConstDouble*)kDp45Coef;
+    __device__ __forceinline__ void next()
+    {
+        if constexpr (LOAD) p = opaque_const(p);
+    }
+    __device__ __forceinline__ double operator[](int i) const { return LOAD ? p[i] : kDp45[i]; }
+};
 
 // The sincos64 coefficients in constant memory: the stage loop reads them once
 // per attempt (two scalar loads) through an opaque pointer, and all six
@@ -633,6 +648,17 @@ struct SinCosLoad {
     ConstDouble* p;
     __device__ double operator()(int i) const { return p[i]; }
 };
+
+// The analytic metric's stages load the sine/cosine coefficients; the
+// tabulated metric does not evaluate them in its right-hand side.
+template <int KIND>
+__device__ __forceinline__ auto sincos_source()
+{
+    if constexpr (KIND == 0)
+        return SinCosLoad{opaque_const((ConstDouble*)kSinCos64Const)};
+    else
+        return SinCosImm{};
+}
 template <int KIND>
 __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
                                          Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
@@ -641,38 +667,39 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
     const double a = R.a;
     Deriv<double> k2, k3, k4, k5, k6;
     double Hd, cd;
-    const SinCosLoad sc{opaque_const((ConstDouble*)kSinCos64Const)};
-    ConstDouble* K = opaque_const((ConstDouble*)kDp45Coef);
+    const auto sc = sincos_source<KIND>();
+    Dp45Source<KIND == 0> K;
+    K.next();
     {
         const double A21 = K[0];
         M.rhs(a, fma(h, A21 * k1.r, R.r), fma(h, A21 * k1.th, R.th), fma(h, A21 * k1.pr, R.pr),
               fma(h, A21 * k1.pth, R.pth), R.pt, R.pph, k2, Hd, cd, sc);
     }
-    K = opaque_const(K);
+    K.next();
     {
         const double A31 = K[1], A32 = K[2];
 #define TT_S3(c) fma(h, fma(A32, k2.c, A31 * k1.c), R.c)
         M.rhs(a, TT_S3(r), TT_S3(th), TT_S3(pr), TT_S3(pth), R.pt, R.pph, k3, Hd, cd, sc);
     }
-    K = opaque_const(K);
+    K.next();
     {
         const double A41 = K[3], A42 = K[4], A43 = K[5];
 #define TT_S4(c) fma(h, fma(A43, k3.c, fma(A42, k2.c, A41 * k1.c)), R.c)
         M.rhs(a, TT_S4(r), TT_S4(th), TT_S4(pr), TT_S4(pth), R.pt, R.pph, k4, Hd, cd, sc);
     }
-    K = opaque_const(K);
+    K.next();
     {
         const double A51 = K[6], A52 = K[7], A53 = K[8], A54 = K[9];
 #define TT_S5(c) fma(h, fma(A54, k4.c, fma(A53, k3.c, fma(A52, k2.c, A51 * k1.c))), R.c)
         M.rhs(a, TT_S5(r), TT_S5(th), TT_S5(pr), TT_S5(pth), R.pt, R.pph, k5, Hd, cd, sc);
     }
-    K = opaque_const(K);
+    K.next();
     {
         const double A61 = K[10], A62 = K[11], A63 = K[12], A64 = K[13], A65 = K[14];
 #define TT_S6(c) fma(h, fma(A65, k5.c, fma(A64, k4.c, fma(A63, k3.c, fma(A62, k2.c, A61 * k1.c)))), R.c)
         M.rhs(a, TT_S6(r), TT_S6(th), TT_S6(pr), TT_S6(pth), R.pt, R.pph, k6, Hd, cd, sc);
     }
-    K = opaque_const(K);
+    K.next();
     {
         const double B1 = K[15], B3 = K[16], B4 = K[17], B5 = K[18], B6 = K[19];
 #define TT_Y5(c) fma(h, fma(B6, k6.c, fma(B5, k5.c, fma(B4, k4.c, fma(B3, k3.c, B1 * k1.c)))), R.c)
@@ -684,7 +711,7 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
         y5.pth = TT_Y5(pth);
     }
     M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, sc);
-    K = opaque_const(K);
+    K.next();
     {
         const double E1 = K[20], E3 = K[21], E4 = K[22], E5 = K[23], E6 = K[24], E7 = K[25];
 #define TT_E(c) h * fma(E7, k7.c, fma(E6, k6.c, fma(E5, k5.c, fma(E4, k4.c, fma(E3, k3.c, E1 * k1.c)))))
