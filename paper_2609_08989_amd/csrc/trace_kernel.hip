@@ -88,21 +88,36 @@ struct Pair<METHOD_RKF45> {
                                     28561.0 / 56430.0 - 2197.0 / 4104.0, -9.0 / 50.0 + 1.0 / 5.0, 2.0 / 55.0};
 };
 
-// sum_j w[j] k[j] over the nonzero weights (known at compile time once
-// unrolled): the first term a product, the rest fused in index order.
-template <int N>
-__device__ __forceinline__ double weighted(const double (&w)[N], const double (&k)[N])
+// Rows of a pair's tableau as compile-time weight functions over the six
+// stage slopes: stage S's a[S][.], the propagated b and the error e.
+template <class P, int S>
+struct RowA {
+    static constexpr double w(int j) { return j < 5 ? P::a[S][j] : 0.0; }
+};
+template <class P>
+struct RowB {
+    static constexpr double w(int j) { return P::b[j]; }
+};
+template <class P>
+struct RowE {
+    static constexpr double w(int j) { return P::e[j]; }
+};
+
+// sum_j w(j) k[j] over the nonzero compile-time weights of Row: the first term
+// a product, the rest fused in index order.  Zero weights generate no code and
+// no test (the row and the index are template arguments).
+template <class Row, int J = 0, bool STARTED = false>
+__device__ __forceinline__ double weighted(const double (&k)[6], double acc = 0.0)
 {
-    double acc = 0.0;
-    bool first = true;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        if (w[j] != 0.0) {
-            acc = first ? w[j] * k[j] : fma(w[j], k[j], acc);
-            first = false;
-        }
+    if constexpr (J == 6) {
+        return acc;
+    } else if constexpr (Row::w(J) == 0.0) {
+        return weighted<Row, J + 1, STARTED>(k, acc);
+    } else if constexpr (!STARTED) {
+        return weighted<Row, J + 1, true>(k, Row::w(J) * k[J]);
+    } else {
+        return weighted<Row, J + 1, true>(k, fma(Row::w(J), k[J], acc));
     }
-    return acc;
 }
 
 enum { CLS_ESCAPED = 0, CLS_CAPTURED = 1, CLS_FAILED = 2, CLS_ON_DISK = 3 };
@@ -732,49 +747,62 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
 
 // One attempted step of a six-stage pair (Cash-Karp or Fehlberg) with FP64
 // stages: the same outputs as stages64.
+// Stage slopes of a six-stage pair, by component.
+struct SixSlopes {
+    double t[6], r[6], th[6], ph[6], pr[6], pth[6];
+};
+
+// Stages S..5 of a six-stage pair: the stage argument from the compile-time
+// row a[S] (zero weights drop out), then its slope.
+template <int KIND, class P, int S, class Coef>
+__device__ __forceinline__ void six_stage(const Ray& R, const MetricOps<KIND>& M_, double h, SixSlopes& k, Coef sc)
+{
+    if constexpr (S < 6) {
+        using W = RowA<P, S>;
+        Deriv<double> ks;
+        double Hd, cd;
+        M_.rhs(R.a, fma(h, weighted<W>(k.r), R.r), fma(h, weighted<W>(k.th), R.th), fma(h, weighted<W>(k.pr), R.pr),
+               fma(h, weighted<W>(k.pth), R.pth), R.pt, R.pph, ks, Hd, cd, sc);
+        k.t[S] = ks.t;
+        k.r[S] = ks.r;
+        k.th[S] = ks.th;
+        k.ph[S] = ks.ph;
+        k.pr[S] = ks.pr;
+        k.pth[S] = ks.pth;
+        six_stage<KIND, P, S + 1>(R, M_, h, k, sc);
+    }
+}
+
 template <int KIND, int M>
 __device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>& M_, double h, Deriv<double>& y5,
                                              Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
 {
     using P = Pair<M>;
-    const double a = R.a;
-    // component-wise stage derivatives kc[stage] for the dynamic components
-    double kt[6], kr[6], kth[6], kph[6], kpr[6], kpth[6];
-    kt[0] = R.k.t;
-    kr[0] = R.k.r;
-    kth[0] = R.k.th;
-    kph[0] = R.k.ph;
-    kpr[0] = R.k.pr;
-    kpth[0] = R.k.pth;
-#pragma unroll
-    for (int s = 1; s < 6; ++s) {
-        double w[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int j = 0; j < 5; ++j) w[j] = P::a[s][j];
-        Deriv<double> ks;
-        double Hd, cd;
-        M_.rhs(a, fma(h, weighted(w, kr), R.r), fma(h, weighted(w, kth), R.th), fma(h, weighted(w, kpr), R.pr),
-               fma(h, weighted(w, kpth), R.pth), R.pt, R.pph, ks, Hd, cd);
-        kt[s] = ks.t;
-        kr[s] = ks.r;
-        kth[s] = ks.th;
-        kph[s] = ks.ph;
-        kpr[s] = ks.pr;
-        kpth[s] = ks.pth;
-    }
-    y5.t = fma(h, weighted(P::b, kt), R.t);
-    y5.r = fma(h, weighted(P::b, kr), R.r);
-    y5.th = fma(h, weighted(P::b, kth), R.th);
-    y5.ph = fma(h, weighted(P::b, kph), R.ph);
-    y5.pr = fma(h, weighted(P::b, kpr), R.pr);
-    y5.pth = fma(h, weighted(P::b, kpth), R.pth);
-    M_.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
-    e.t = h * weighted(P::e, kt);
-    e.r = h * weighted(P::e, kr);
-    e.th = h * weighted(P::e, kth);
-    e.ph = h * weighted(P::e, kph);
-    e.pr = h * weighted(P::e, kpr);
-    e.pth = h * weighted(P::e, kpth);
+    // component-wise stage derivatives k.c[stage] for the dynamic components
+    SixSlopes k;
+    k.t[0] = R.k.t;
+    k.r[0] = R.k.r;
+    k.th[0] = R.k.th;
+    k.ph[0] = R.k.ph;
+    k.pr[0] = R.k.pr;
+    k.pth[0] = R.k.pth;
+    const auto sc = sincos_source<KIND>();
+    six_stage<KIND, P, 1>(R, M_, h, k, sc);
+    using B = RowB<P>;
+    y5.t = fma(h, weighted<B>(k.t), R.t);
+    y5.r = fma(h, weighted<B>(k.r), R.r);
+    y5.th = fma(h, weighted<B>(k.th), R.th);
+    y5.ph = fma(h, weighted<B>(k.ph), R.ph);
+    y5.pr = fma(h, weighted<B>(k.pr), R.pr);
+    y5.pth = fma(h, weighted<B>(k.pth), R.pth);
+    M_.rhs(R.a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, sc);
+    using E = RowE<P>;
+    e.t = h * weighted<E>(k.t);
+    e.r = h * weighted<E>(k.r);
+    e.th = h * weighted<E>(k.th);
+    e.ph = h * weighted<E>(k.ph);
+    e.pr = h * weighted<E>(k.pr);
+    e.pth = h * weighted<E>(k.pth);
 }
 
 // Gragg-Bulirsch-Stoer extrapolation (Sec. 3.2).  A macro-step h is covered
