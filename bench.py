@@ -78,20 +78,38 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+def _committed_counters():
+    """The headline kernel's committed rocprofv3 figures, if they were taken on
+    these kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    return t if t.get("source_sha256") == kernel_source_hash() else None
+
+
 def measured_traffic():
     """HBM bytes per launch of the headline kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), if they were taken on these
     kernel sources; else None.  The bytes are the per-ray records, outputs and
     job tables of the image, which do not depend on the launch shape; the
     shape they were measured at is returned with them."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except OSError:
-        return None, None
-    if t.get("source_sha256") != kernel_source_hash():
+    t = _committed_counters()
+    if t is None:
         return None, None
     return float(t["fetch_bytes"] + t["write_bytes"]), t.get("launch")
+
+
+def attempts_histogram(att) -> dict:
+    """Attempted steps per ray: quantiles and counts per power-of-two bin
+    (key k counts rays with 2^k <= attempts < 2^(k+1))."""
+    import numpy as np
+    att = np.asarray(att, dtype=np.int64)
+    q = {f"p{p}": float(np.percentile(att, p)) for p in (0, 10, 50, 90, 99, 100)}
+    k = np.floor(np.log2(np.maximum(att, 1))).astype(int)
+    q["log2_bins"] = {str(int(b)): int(c) for b, c in zip(*np.unique(k, return_counts=True))}
+    return q
 
 
 def shape(L):
@@ -320,6 +338,20 @@ def main():
     achieved = flops / (kern_ms * 1e-3) / 1e12
     att = o["n_accept"] + o["n_reject"]
     traffic_bytes, traffic_shape = measured_traffic()
+    cnt = _committed_counters()
+    executed = None
+    if cnt is not None and cnt.get("executed_fp64_flop"):
+        ex = float(cnt["executed_fp64_flop"])
+        executed = {"flop_per_launch": ex, "achieved": ex / (kern_ms * 1e-3) / 1e12,
+                    "frac": ex / (kern_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                    "note": "FP64 VALU instructions x lanes x lane efficiency from the committed counters "
+                            "(FMA = 2), over this run's kernel time"}
+    sh0 = dict(zip(SHAPE_KEYS, tuned.get("fp64", [0, 0, 0, 0, 0])))
+    launched = (sh0["block_threads"] // 64 * sh0["blocks_per_cu"] / 4.0
+                if sh0["block_threads"] > 0 and sh0["blocks_per_cu"] > 0 else None)
+    occupancy = {"launched_waves_per_simd": launched, "max_waves_per_simd": 2,
+                 "mean_resident_waves_per_simd": (cnt or {}).get("mean_resident_waves_per_simd"),
+                 "counter_launch_shape": (cnt or {}).get("launch")}
     result = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -327,13 +359,14 @@ def main():
         "config": {"workload": "kerr_a0.9_i60deg_r1000_512x512_disk_isco_to_20M", "rays": n,
                    "rtol": GATE_RTOL, "atol": GATE_ATOL, "precision": "fp64",
                    "gate_h_max": h_gate_max, "gate_holds": bool(h_gate_max <= 1e-8),
-                   "failed_rays": int((o["cls"] == 2).sum()), "attempts_per_ray": float(att.mean())},
+                   "failed_rays": int((o["cls"] == 2).sum()), "attempts_per_ray": float(att.mean()),
+                   "attempts_histogram": attempts_histogram(att)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic_bytes, "traffic_launch_shape": traffic_shape,
                      "kernel": "trace_persistent<0,0> (analytic Kerr, FP64)",
                      "kernel_ms": kern_ms, "flop_per_launch": flops,
-                     "flop_per_attempt": FLOP_ATTEMPT},
+                     "flop_per_attempt": FLOP_ATTEMPT, "executed": executed, "occupancy": occupancy},
     }
 
     # ---- extra legs at the config tolerance rtol = 1e-8

@@ -1,0 +1,51 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the attempts
+histogram, and the rule that committed counters count only for the kernel
+sources they were taken on."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    return b
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_attempts_histogram():
+    b = load_bench()
+    att = np.array([1, 2, 3, 201, 230, 255, 256, 780])
+    h = b.attempts_histogram(att)
+    assert h["p0"] == 1.0 and h["p100"] == 780.0
+    assert h["log2_bins"] == {"0": 1, "1": 2, "7": 3, "8": 1, "9": 1}
+    assert sum(h["log2_bins"].values()) == att.size
+
+
+def test_counters_only_for_matching_sources(tmp_path, monkeypatch):
+    b = load_bench()
+    good = {"source_sha256": b.kernel_source_hash(), "fetch_bytes": 1.0, "write_bytes": 2.0,
+            "launch": "256,1,1,4,2", "executed_fp64_flop": 5.0}
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps(good))
+    monkeypatch.setattr(b, "TRAFFIC_FILE", str(f))
+    assert b.measured_traffic() == (3.0, "256,1,1,4,2")
+    assert b._committed_counters()["executed_fp64_flop"] == 5.0
+    f.write_text(json.dumps(dict(good, source_sha256="0" * 64)))
+    assert b.measured_traffic() == (None, None)
+    assert b._committed_counters() is None
+    monkeypatch.setattr(b, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
+    assert b.measured_traffic() == (None, None)
