@@ -289,7 +289,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the tracer shards by pixel rows or requests; see DESIGN.md)", file=sys.stderr)
+              "(on several GPUs the tracer would shard by pixel rows or by requests)", file=sys.stderr)
         sys.exit(2)
 
     import torch
