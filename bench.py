@@ -136,6 +136,18 @@ def time_leg(T, torch, args_tuple, out, steps, warmup, launch=None):
     return wall, kernel_total_ms / launches
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, solver, seconds: float) -> dict:
     import oracle
     oracle.build(force=False)
@@ -154,6 +166,7 @@ def cpu_baseline(w, solver, seconds: float) -> dict:
     oracle.trace(m, c, d, s, ray_ids=ids)
     dt = time.perf_counter() - t
     return {"value": n / dt, "unit": "rays/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{n} seeded-random pixels of the same 512x512 image (rtol={solver['rtol']:g}), "
                       f"plain FP64 C oracle, OpenMP over pixels, {dt:.1f} s"}
 
