@@ -85,3 +85,22 @@ def test_sincos32_accuracy(lib):
     uc = np.abs(c - ec) / np.spacing(np.maximum(np.abs(ec), 1e-30).astype(np.float32))
     assert us[np.abs(es) > 1e-3].max() <= 2.0 and uc[np.abs(ec) > 1e-3].max() <= 2.0
     assert np.abs(s - es).max() < 1.2e-7 and np.abs(c - ec).max() < 1.2e-7
+
+
+def test_sincos_wide_arguments_and_quadrants(lib):
+    """Up to the documented |x| < 1e6 (quadrant index k up to ~6.4e5): the
+    three-part reduction and the 32-bit quadrant keep 2 ulp for |sin|, |cos| >
+    1e-3, every quadrant of negative and positive k included."""
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.uniform(-1e6, 1e6, 100000), rng.uniform(-1e3, 1e3, 100000),
+                        np.pi / 2 * np.arange(-40, 41) + 0.3])
+    s, c = run(lib, x)
+    es, ec = np.sin(x), np.cos(x)
+    us = np.abs(s - es) / np.spacing(np.abs(es))
+    uc = np.abs(c - ec) / np.spacing(np.abs(ec))
+    assert us[np.abs(es) > 1e-3].max() <= 2.0 and uc[np.abs(ec) > 1e-3].max() <= 2.0
+    # every quadrant q = k mod 4 of both signs of k is exercised above
+    k = np.rint(x * (2 / np.pi)).astype(np.int64)
+    assert set((k[k < 0] % 4).tolist()) == {0, 1, 2, 3} and set((k[k > 0] % 4).tolist()) == {0, 1, 2, 3}
+    s0, c0 = run(lib, np.array([0.0, -0.0]))
+    assert np.all(s0 == 0.0) and np.all(c0 == 1.0)
