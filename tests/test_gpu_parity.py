@@ -377,6 +377,23 @@ def test_launch_shape_invariance(T):
             assert np.array_equal(ref[k], g[k]), k
 
 
+@pytest.mark.parametrize("method", [1, 2, 3, 4])
+def test_launch_shape_invariance_other_methods(T, method):
+    """Cash-Karp, Fehlberg, extrapolation and Verlet: the same bits for every
+    launch shape and queue order (lanes share no arithmetic)."""
+    w = W.WORKLOADS["kerr09_512"]
+    if method == 4:
+        cam, sv = VERLET_CAM, verlet_solver(0.05, 1.05)
+    else:
+        cam, sv = dict(w["cameras"][0], nx=72, ny=56), dict(w["solver"], method=method)
+    ref = gpu_trace(T, w["a"], cam, w["disk"], sv, launch=T.make_launch(order=T.ORDER_PIXEL))
+    for shape in ((64, 2, 16, 1, T.ORDER_COST), (256, 1, 1, 4, T.ORDER_TILE), (128, 0, 64, 8, T.ORDER_DEFAULT)):
+        say("method", method, "launch", shape)
+        g = gpu_trace(T, w["a"], cam, w["disk"], sv, launch=T.make_launch(*shape))
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (method, shape, k)
+
+
 def test_tile_order_ragged_cameras(T):
     """8 x 8 tile order on cameras whose sides are not multiples of 8 (edge
     tiles are smaller), three cameras in one trace: every pixel is traced once
