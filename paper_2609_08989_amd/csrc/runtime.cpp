@@ -114,15 +114,18 @@ int ktime_collect(double& total_ms, long long& launches)
 {
     total_ms = 0.0;
     launches = 0;
-    for (auto& pr : g_dev.ktime_pending) {
+    // a pair leaves the pending list only once it has been read, so an error
+    // part-way leaves the unread pairs pending and none in both lists
+    while (!g_dev.ktime_pending.empty()) {
+        const auto pr = g_dev.ktime_pending.front();
         HIP_TRY(hipEventSynchronize(pr.second));
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
         total_ms += ms;
         ++launches;
+        g_dev.ktime_pending.erase(g_dev.ktime_pending.begin());
         g_dev.ktime_spare.push_back(pr);
     }
-    g_dev.ktime_pending.clear();
     return TARTARUS_OK;
 }
 
@@ -460,14 +463,23 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
             g_dev.ktime_spare.pop_back();
         } else {
             HIP_TRY(hipEventCreate(&kt.first));
-            HIP_TRY(hipEventCreate(&kt.second));
+            const hipError_t e = hipEventCreate(&kt.second);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(kt.first);
+                return hip_fail(e, "hipEventCreate");
+            }
         }
-        HIP_TRY(hipEventRecord(kt.first, stream));
-    }
-    HIP_TRY(tartarus_launch_trace(kind, prec, method, &A, grid, L.block_threads, stream));
-    if (kt.first) {
-        HIP_TRY(hipEventRecord(kt.second, stream));
+        // the pair goes back to the pool if the launch cannot be enqueued
+        hipError_t e = hipEventRecord(kt.first, stream);
+        if (e == hipSuccess) e = tartarus_launch_trace(kind, prec, method, &A, grid, L.block_threads, stream);
+        if (e == hipSuccess) e = hipEventRecord(kt.second, stream);
+        if (e != hipSuccess) {
+            g_dev.ktime_spare.push_back(kt);
+            return hip_fail(e, "integrator launch");
+        }
         g_dev.ktime_pending.push_back(kt);
+    } else {
+        HIP_TRY(tartarus_launch_trace(kind, prec, method, &A, grid, L.block_threads, stream));
     }
     for (int c0 = 0; c0 < ncams; c0 += 65535)
         HIP_TRY(tartarus_launch_finish(&A, c0, std::min(65535, ncams - c0), per, stream));
