@@ -20,14 +20,17 @@
  *     a fixed-step symmetric (generalized Stormer-)Verlet scheme;
  *     horizon / escape / equatorial-disk events
  *     refined by bisection on the step's cubic Hermite interpolant to about
- *     1e-12 in the affine parameter.
+ *     1e-12 in the affine parameter (for the extrapolation, whose macro-steps
+ *     are too long for a cubic, by bisection on its own solution over the
+ *     partial step).
  *   - Sec. 4.1, Eq. (17): the constraint residual |H| at every accepted step.
  *
  * Readings where the paper is silent (kept identical on the HIP side, each
  * written out where it is used): the tetrad's e_(t)^phi component, the pixel
  * grid, the sign flip used for backward tracing, the step-size controller,
  * the failure limits, the event rules and the bisection count, the
- * extrapolation's substep sequence, column count and error estimate, the
+ * extrapolation's substep sequence, column count, error estimate, rounding
+ * floor, power-of-two step factor and event location, the
  * Verlet scheme for a non-separable Hamiltonian and its step, the emitter's
  * Keplerian angular velocity, the a = 0 guard in the flux sum.
  *
@@ -38,6 +41,7 @@
  */
 #include "tartarus_oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -505,40 +509,64 @@ void or_dp45_fixed(int n, or_user_rhs f, double* y, double h, int nsteps, double
 /*   T[j][k+1] = T[j][k] + (T[j][k] - T[j-1][k]) / ((n_j/n_{j-k})^2 - 1). */
 /* The diagonal T[K][K] propagates the solution and the difference to    */
 /* T[K][K-1] is the error estimate driving the macro-step control.       */
+/* The sweeps and the tableau carry increments z - y (the extrapolation  */
+/* is linear, so this is the same scheme), which keeps the rounding of   */
+/* the estimate at the size of the step's change instead of the state's. */
 /* ------------------------------------------------------------------ */
 #define GBS_KMAX 8
 
 static int gbs_substeps(int j) { return 2 * j; }
 
-/* Gragg's modified midpoint rule: m substeps of size hs = H/m from y, where
- * k1 = f(y):  z_0 = y,  z_1 = z_0 + hs f(z_0),  z_{i+1} = z_{i-1} + 2 hs f(z_i),
- * followed by the smoothing step  (z_m + z_{m-1} + hs f(z_m)) / 2. */
+/* Gragg's modified midpoint rule on increments: m substeps of size hs = H/m
+ * from y, where k1 = f(y):  d_0 = 0,  d_1 = hs f(y),  d_{i+1} = d_{i-1} +
+ * 2 hs f(y + d_i), followed by the smoothing step (d_m + d_{m-1} + hs f(y +
+ * d_m)) / 2; out = the smoothed increment. */
 static void modified_midpoint(int n, rhs_fn f, void* ctx, const double* y, const double* k1, double H, int m,
                               double* out)
 {
     double hs = H / (double)m;
-    double zprev[16], z[16], znext[16], dz[16];
-    for (int d = 0; d < n; ++d) {
-        zprev[d] = y[d];
-        z[d] = y[d] + hs * k1[d];
+    double dprev[16], d[16], dnext[16], z[16], dz[16];
+    for (int q = 0; q < n; ++q) {
+        dprev[q] = 0.0;
+        d[q] = hs * k1[q];
     }
     for (int i = 1; i < m; ++i) {
+        for (int q = 0; q < n; ++q) z[q] = y[q] + d[q];
         f(ctx, z, dz);
-        for (int d = 0; d < n; ++d) znext[d] = zprev[d] + 2.0 * hs * dz[d];
-        for (int d = 0; d < n; ++d) { zprev[d] = z[d]; z[d] = znext[d]; }
+        for (int q = 0; q < n; ++q) dnext[q] = dprev[q] + 2.0 * hs * dz[q];
+        for (int q = 0; q < n; ++q) { dprev[q] = d[q]; d[q] = dnext[q]; }
     }
+    for (int q = 0; q < n; ++q) z[q] = y[q] + d[q];
     f(ctx, z, dz);
-    for (int d = 0; d < n; ++d) out[d] = 0.5 * (zprev[d] + z[d] + hs * dz[d]);
+    for (int q = 0; q < n; ++q) out[q] = 0.5 * (dprev[q] + d[q] + hs * dz[q]);
 }
 
+/* Rounding floor of the extrapolation's error estimate (a reading: the
+ * paper gives no controller).  Far from the hole the truncation error of a
+ * macro-step falls below the rounding of the difference T[K][K] - T[K][K-1],
+ * and a step factor taken from rounding noise differs between any two
+ * correct FP64 evaluations.  A component whose estimate is at most
+ * GBS_FLOOR_ULPS ulps of the largest increment of that component among the
+ * sweeps, capped at GBS_FLOOR_TOL of its tolerance scale, is taken as zero;
+ * the threshold sits far above the rounding noise (tens of ulps), so both
+ * evaluations fall on the same side of it, and the cap keeps the tolerance's
+ * meaning at tight tolerances. */
+#define GBS_FLOOR_ULPS 262144.0      /* 2^18 */
+#define GBS_FLOOR_TOL 0.01
+
 /* One macro-step with K columns from y (k1 = f(y)): writes T[K][K], the error
- * vector T[K][K] - T[K][K-1] and f(T[K][K]). */
+ * vector T[K][K] - T[K][K-1] with the rounding floor applied for the
+ * tolerance (atol, rtol) (rtol = atol = 0: no floor), and f(T[K][K]) (knew
+ * may be NULL). */
 static void gbs_attempt(int K, int n, rhs_fn f, void* ctx, const double* y, const double* k1, double H,
-                        double* ynew, double* err, double* knew)
+                        double atol, double rtol, double* ynew, double* err, double* knew)
 {
     double T[GBS_KMAX][GBS_KMAX][16];
+    double big[16];
+    for (int d = 0; d < n; ++d) big[d] = 0.0;
     for (int j = 1; j <= K; ++j) {
         modified_midpoint(n, f, ctx, y, k1, H, gbs_substeps(j), T[j - 1][0]);
+        for (int d = 0; d < n; ++d) big[d] = fmax(big[d], fabs(T[j - 1][0][d]));
         for (int k = 1; k < j; ++k) {
             double ratio = (double)gbs_substeps(j) / (double)gbs_substeps(j - k);
             double den = ratio * ratio - 1.0;
@@ -547,10 +575,14 @@ static void gbs_attempt(int K, int n, rhs_fn f, void* ctx, const double* y, cons
         }
     }
     for (int d = 0; d < n; ++d) {
-        ynew[d] = T[K - 1][K - 1][d];
-        err[d] = T[K - 1][K - 1][d] - T[K - 1][K - 2][d];
+        ynew[d] = y[d] + T[K - 1][K - 1][d];
+        double e = T[K - 1][K - 1][d] - T[K - 1][K - 2][d];
+        double floor_ = GBS_FLOOR_ULPS * DBL_EPSILON * big[d];
+        double cap = GBS_FLOOR_TOL * (atol + rtol * fmax(fabs(y[d]), fabs(ynew[d])));
+        if (cap < floor_) floor_ = cap;
+        err[d] = fabs(e) <= floor_ ? 0.0 : e;
     }
-    f(ctx, ynew, knew);
+    if (knew) f(ctx, ynew, knew);
 }
 
 /* Columns of the extrapolation used to trace rays (orders 2K and 2K - 2). */
@@ -564,7 +596,7 @@ void or_gbs_fixed(int K, int n, or_user_rhs f, double* y, double h, int nsteps, 
     if (K < 2 || K > GBS_KMAX) return;
     f(y, k1, n);
     for (int s = 0; s < nsteps; ++s) {
-        gbs_attempt(K, n, user_tramp, &u, y, k1, h, yn, e, kn);
+        gbs_attempt(K, n, user_tramp, &u, y, k1, h, 0.0, 0.0, yn, e, kn);
         for (int d = 0; d < n; ++d) { y[d] = yn[d]; k1[d] = kn[d]; last_err[d] = e[d]; }
     }
 }
@@ -688,10 +720,25 @@ enum { EV_DISK = 0, EV_HORIZON = 1, EV_ESCAPE = 2 };
 typedef struct {
     const double *y0, *y1, *k1, *k7;
     double h;
+    const or_metric* reint;   /* non-NULL: the extrapolation's own solution */
 } step_ctx;
 
+static void kerr_rhs_tramp(void* ctx, const double* y, double* dy);
+
+/* Component comp of the step's solution at lambda_n + s h.  The 5(4) pairs
+ * and Verlet read it off the cubic Hermite interpolant.  A macro-step of the
+ * extrapolation spans up to hundreds of M, over which a cubic is accurate to
+ * ~1e-3 only; there the point is one macro-step of length s h from the
+ * step's start (the same sweeps and columns, without error control). */
 static double interp(const step_ctx* st, int comp, double s)
 {
+    if (st->reint) {
+        double ys[NSTATE], es[NSTATE];
+        if (s == 0.0) return st->y0[comp];
+        gbs_attempt(OR_GBS_COLUMNS, NSTATE, kerr_rhs_tramp, (void*)st->reint, st->y0, st->k1, s * st->h, 0.0, 0.0,
+                    ys, es, NULL);
+        return ys[comp];
+    }
     return or_hermite(s, st->y0[comp], st->k1[comp], st->y1[comp], st->k7[comp], st->h);
 }
 
@@ -736,6 +783,18 @@ static int all_finite(const double* y)
     for (int d = 0; d < NSTATE; ++d)
         if (!isfinite(y[d])) return 0;
     return 1;
+}
+
+/* The largest power of two not above x (x > 0, finite): the extrapolation's
+ * step factor (a reading, with its rounding floor: steps stay h0 * 2^k, so
+ * two correct FP64 evaluations, whose error estimates differ by rounding,
+ * take the same step sizes unless an estimate lies within rounding of a
+ * power-of-two boundary of the factor or of the acceptance threshold). */
+static double pow2_floor(double x)
+{
+    int e;
+    frexp(x, &e);
+    return ldexp(1.0, e - 1);
 }
 
 /* Integrate one ray from the initial state y0 with first step h0.  When rec
@@ -789,7 +848,8 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
             err = 0.0;
         } else {
             if (sv->method == OR_METHOD_GBS)
-                gbs_attempt(OR_GBS_COLUMNS, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
+                gbs_attempt(OR_GBS_COLUMNS, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, sv->atol, sv->rtol, y5, e,
+                            k7);
             else
                 rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
             /* RMS error norm over all eight components */
@@ -805,6 +865,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
             /* rejected (a NaN or infinite error also lands here) */
             out->n_reject++;
             double fac = isnan(err) ? 0.2 : fmax(0.2, 0.9 * pow(err, expo));
+            if (sv->method == OR_METHOD_GBS) fac = pow2_floor(fac);
             h *= fac;
             rejected_prev = 1;
             if (h < 1e-14 * fmax(1.0, fabs(lambda))) break;
@@ -814,7 +875,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
         if (!all_finite(y5)) break;
 
         /* events on the accepted step [lambda, lambda + h] */
-        step_ctx st = {y, y5, k1, k7, h};
+        step_ctx st = {y, y5, k1, k7, h, sv->method == OR_METHOD_GBS ? m : NULL};
         double ev_s[3];
         int ev_kind[3], nev = 0;
         double ch0 = y[R_] - r_stop, ch1 = y5[R_] - r_stop;
@@ -899,6 +960,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
         double fmax_ = rejected_prev ? 1.0 : 10.0;
         double fac = err == 0.0 ? fmax_ : fmin(fmax_, fmax(0.2, 0.9 * pow(err, expo)));
         if (sv->method == OR_METHOD_VERLET) fac = 1.0;
+        if (sv->method == OR_METHOD_GBS) fac = pow2_floor(fac);
         lambda += h;
         for (int d = 0; d < NSTATE; ++d) { y[d] = y5[d]; k1[d] = k7[d]; }
         h *= fac;

@@ -168,11 +168,12 @@ def deflection_leg(alpha):
     return leg
 
 
-@pytest.mark.parametrize("method", [0, 1, 2], ids=["dp45", "ck45", "rkf45"])
+@pytest.mark.parametrize("method", [0, 1, 2, 3], ids=["dp45", "ck45", "rkf45", "gbs"])
 @pytest.mark.parametrize("alpha", [6.5, 9.0, 15.0])
 def test_schwarzschild_deflection_quadrature(orc, alpha, method):
     """Equatorial escape: total phi swept between r = 1000 (start) and r = 1100 (stop),
-    with each 5(4) pair of Sec. 3.2."""
+    with each 5(4) pair of Sec. 3.2 and the extrapolation (whose escape point is
+    located on its own solution over the partial macro-step)."""
     leg = deflection_leg(alpha)
     expect = leg(1 / D) + leg(1 / 1100.0)
     o = single_ray(orc, 0.0, 90.0, alpha, 0.0, solver=W.solver(rtol=1e-12, atol=1e-14, method=method))
@@ -186,10 +187,7 @@ def test_schwarzschild_deflection_quadrature(orc, alpha, method):
 @pytest.mark.parametrize("alpha", [6.5, 9.0, 15.0])
 def test_schwarzschild_deflection_at_accepted_states(orc, alpha, method):
     """The integrated solution itself: at every accepted state on the outgoing
-    leg, phi equals the orbit quadrature at that state's r.  (For the
-    extrapolation method the escape point is read off the cubic Hermite
-    interpolant of a macro-step several hundred M long, which limits the
-    final phi to ~1e-5; the accepted states carry the method's accuracy.)"""
+    leg, phi equals the orbit quadrature at that state's r."""
     leg = deflection_leg(alpha)
     c = dict(r_obs=D, theta_obs=math.pi / 2, nx=1, ny=1, alpha_min=alpha, alpha_max=alpha, beta_min=0.0,
              beta_max=0.0)
@@ -549,3 +547,65 @@ def test_tabulated_path_sensitivity_sets_its_tolerance(orc):
     th = np.abs(o1["final_rtp"][:, 1] / o0["final_rtp"][:, 1] - 1)
     assert max(rel.max(), th.max()) > 1e-8        # far above rounding ...
     assert max(rel.max(), th.max()) < 1e-5        # ... and inside the bar
+
+
+def _kerr_disk_image(orc, method, rtol, nx=24, ny=20, fma=False):
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=nx, ny=ny, alpha_min=-12.0, alpha_max=12.0, beta_min=-10.0, beta_max=10.0)
+    sv = dict(w["solver"], rtol=rtol, atol=rtol / 100, method=method)
+    return orc.trace(orc.make_metric(w["a"]), [orc.make_camera(cam)], orc.make_disk(w["disk"]),
+                     orc.make_solver(sv), fma=fma)
+
+
+def test_extrapolation_disk_hits_match_dormand_prince(orc):
+    """Disk crossings of the extrapolation are located on its own solution over
+    the partial macro-step: at rtol 1e-10 its hit radius and redshift agree
+    with Dormand-Prince at rtol 1e-12 (another method, far more accurate) to
+    5e-8 (measured 1.6e-8; Dormand-Prince itself at rtol 1e-10 is 3e-7 off),
+    where a cubic over the macro-step was off by ~1e-3."""
+    ref = _kerr_disk_image(orc, 0, 1e-12)
+    g = _kerr_disk_image(orc, 3, 1e-10)
+    same = (ref["cls"] == g["cls"]) & (ref["n_hits"] == g["n_hits"])
+    assert same.mean() > 0.98
+    m = same & (ref["n_hits"] > 0)
+    assert m.sum() > 60
+    for k in range(2):
+        mk = same & (ref["n_hits"] > k)
+        assert np.abs(g["hit_r"][mk, k] / ref["hit_r"][mk, k] - 1).max() < 5e-8
+        assert np.abs(g["hit_g"][mk, k] / ref["hit_g"][mk, k] - 1).max() < 5e-8
+    esc = same & (ref["cls"] == orc.ESCAPED)
+    assert np.abs(g["final_rtp"][esc, 1] - ref["final_rtp"][esc, 1]).max() < 5e-8
+
+
+def test_extrapolation_steps_are_powers_of_two_of_the_first(orc):
+    """The extrapolation's step factor is the largest power of two not above the
+    elementary controller's factor, so every accepted macro-step is h0 2^k."""
+    m = orc.make_metric(0.9)
+    c = dict(r_obs=1000.0, theta_obs=1.0, nx=1, ny=1, alpha_min=8.0, alpha_max=8.0, beta_min=5.0, beta_max=5.0)
+    q0 = orc.initial_state(m, orc.make_camera(c), 0, 0)
+    p = orc.trace_path(m, q0, 10.0, orc.make_disk(None), orc.make_solver(W.solver(method=3)))
+    assert p["cls"] == orc.ESCAPED and p["n_accept"] > 10 and p["n_reject"] > 0
+    h = np.diff(p["lam"]) / 10.0
+    k = np.log2(h)
+    assert np.abs(k - np.round(k)).max() < 1e-9
+    assert len(set(np.round(k).astype(int))) > 4
+
+
+@pytest.mark.parametrize("rtol", [1e-8, 3e-10])
+def test_extrapolation_step_sequence_survives_rounding(orc, rtol):
+    """The reason for the extrapolation's rounding floor and power-of-two factor:
+    the oracle and its FMA-contracted build (two correct FP64 roundings of the
+    same arithmetic) take the same macro-steps on every ray, so their outputs
+    agree to rounding.  (With the plain elementary controller they agreed on
+    the step count of half the rays and differed by 3e-3 in hit radius.)"""
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=37, ny=29)
+    sv = dict(w["solver"], rtol=rtol, atol=rtol / 100, method=3)
+    args = (orc.make_metric(w["a"]), [orc.make_camera(cam)], orc.make_disk(w["disk"]), orc.make_solver(sv))
+    o, f = orc.trace(*args), orc.trace(*args, fma=True)
+    assert np.array_equal(o["n_accept"], f["n_accept"]) and np.array_equal(o["n_reject"], f["n_reject"])
+    assert np.array_equal(o["cls"], f["cls"]) and np.array_equal(o["n_hits"], f["n_hits"])
+    m = o["n_hits"] > 0
+    assert m.sum() > 50
+    assert np.abs(f["hit_r"][m, 0] / o["hit_r"][m, 0] - 1).max() < 1e-12
+    assert np.abs(f["final_rtp"][:, 1] / o["final_rtp"][:, 1] - 1).max() < 1e-11
