@@ -29,8 +29,9 @@
  * written out where it is used): the tetrad's e_(t)^phi component, the pixel
  * grid, the sign flip used for backward tracing, the step-size controller,
  * the failure limits, the event rules and the bisection count, the
- * extrapolation's substep sequence, column count, error estimate, rounding
- * floor, power-of-two step factor and event location, the
+ * rounding floor of the error estimates, the extrapolation's substep
+ * sequence, column count, error estimate, power-of-two step factor and event
+ * location, the
  * Verlet scheme for a non-separable Hamiltonian and its step, the emitter's
  * Keplerian angular velocity, the a = 0 guard in the flux sum.
  *
@@ -442,10 +443,23 @@ void or_dp45_tableau(double* c, double* a, double* b, double* bstar) { or_rk_tab
 
 typedef void (*rhs_fn)(void* ctx, const double* y, double* dy);
 
+/* Rounding floor of an embedded pair's error estimate (a reading: the paper
+ * gives no controller).  The estimate h sum_j (b_j - b*_j) k_j of a component
+ * rounds to a few ulps of h |b - b*|_1 max(|k_n|, |k_n+1|); far from the hole
+ * the first steps' estimates are that rounding alone (a cancellation of ~1e9
+ * in the angular components), and a step factor taken from them differs
+ * between two correct FP64 evaluations by ~1e-7, enough for a later estimate
+ * to fall on the other side of 1.  A component whose estimate is at most
+ * RK_FLOOR_ULPS of that scale, capped at RK_FLOOR_TOL of its tolerance scale,
+ * is taken as zero.  (The extrapolation has its own floor, GBS_FLOOR_*.) */
+#define RK_FLOOR_ULPS 262144.0       /* 2^18 */
+#define RK_FLOOR_TOL 0.01
+
 /* One attempted step of size h from y with k1 = f(y): writes the fifth-order
- * solution y5, the error vector err = h * sum (b - b*) k, and k7 = f(y5). */
+ * solution, the error vector (b - b*) h k with the rounding floor applied for
+ * the tolerance (atol, rtol) (rtol = atol = 0: no floor), and k7 = f(y5). */
 static void rk_attempt(int method, int n, rhs_fn f, void* ctx, const double* y, const double* k1, double h,
-                       double* y5, double* err, double* k7)
+                       double atol, double rtol, double* y5, double* err, double* k7)
 {
     const double(*A)[6] = RK_A[method];
     const double* B = RK_B[method];
@@ -467,11 +481,17 @@ static void rk_attempt(int method, int n, rhs_fn f, void* ctx, const double* y, 
         y5[d] = y[d] + h * acc;
     }
     f(ctx, y5, k[6]);
+    double enorm1 = 0.0;
+    for (int j = 0; j < 7; ++j) enorm1 += fabs(B[j] - BS[j]);
     for (int d = 0; d < n; ++d) {
         double acc = 0.0;
         for (int j = 0; j < 7; ++j) acc += (B[j] - BS[j]) * k[j][d];
         err[d] = h * acc;
         k7[d] = k[6][d];
+        double floor_ = RK_FLOOR_ULPS * DBL_EPSILON * enorm1 * fabs(h) * fmax(fabs(k[0][d]), fabs(k[6][d]));
+        double cap = RK_FLOOR_TOL * (atol + rtol * fmax(fabs(y[d]), fabs(y5[d])));
+        if (cap < floor_) floor_ = cap;
+        if (fabs(err[d]) <= floor_) err[d] = 0.0;
     }
 }
 
@@ -489,7 +509,7 @@ void or_rk_fixed(int method, int n, or_user_rhs f, double* y, double h, int nste
     double k1[16], y5[16], e[16], k7[16];
     f(y, k1, n);
     for (int s = 0; s < nsteps; ++s) {
-        rk_attempt(method, n, user_tramp, &u, y, k1, h, y5, e, k7);
+        rk_attempt(method, n, user_tramp, &u, y, k1, h, 0.0, 0.0, y5, e, k7);
         for (int d = 0; d < n; ++d) { y[d] = y5[d]; k1[d] = k7[d]; last_err[d] = e[d]; }
     }
 }
@@ -851,7 +871,7 @@ static void trace_from(const or_metric* m, const double* y0, double h0, const or
                 gbs_attempt(OR_GBS_COLUMNS, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, sv->atol, sv->rtol, y5, e,
                             k7);
             else
-                rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, y5, e, k7);
+                rk_attempt(sv->method, NSTATE, kerr_rhs_tramp, (void*)m, y, k1, h, sv->atol, sv->rtol, y5, e, k7);
             /* RMS error norm over all eight components */
             double acc = 0.0;
             for (int d = 0; d < NSTATE; ++d) {
