@@ -23,10 +23,12 @@
 #include <vector>
 
 #include "../../include/tartarus.h"
+#include "host_logic.hpp"
 #include "internal.hpp"
 #include "order.hpp"
 
 using namespace tartarus;
+using namespace tartarus::host;
 
 extern "C" hipError_t tartarus_launch_trace(int kind, int prec, int method, const LaunchArgs* args, int grid, int block,
                                             hipStream_t stream);
@@ -46,14 +48,6 @@ extern "C" hipError_t tartarus_launch_fill_u64(unsigned long long* p, unsigned l
 
 namespace {
 
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg)
-{
-    g_err = msg;
-    return code;
-}
-
 int hip_fail(hipError_t e, const char* what)
 {
     return fail(TARTARUS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -64,12 +58,6 @@ int hip_fail(hipError_t e, const char* what)
         hipError_t e_ = (expr);                              \
         if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
     } while (0)
-
-// Default mixed-precision regime: FP32 stages where r >= 10 r_+, away from
-// radial (|p_r| < 0.05 |p_t|) and polar (|p_theta| < 0.05 sqrt(Q)) turning points.
-constexpr double kDefaultSwitch = 10.0;
-constexpr double kDefaultTurnR = 0.05;
-constexpr double kDefaultTurnTh = 0.05;
 
 // Per-call launch resources.  A trace copies its job table through pinned host
 // memory into a device table and resets a queue head, then launches; the slot
@@ -158,176 +146,6 @@ int take_slot(int njobs, Slot*& out)
     return TARTARUS_OK;
 }
 
-bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
-
-int check_metric(const tartarus_metric* m, int precision, int method)
-{
-    if (!m) return fail(TARTARUS_E_INVALID, "metric is NULL");
-    if (!(std::isfinite(m->a) && m->a >= 0.0 && m->a < 1.0)) return fail(TARTARUS_E_INVALID, "spin a must be in [0, 1)");
-    if (m->kind == TARTARUS_METRIC_TABLE) {
-        if (!m->table) return fail(TARTARUS_E_INVALID, "tabulated metric needs a table");
-        if (m->nr < 4 || m->nth < 4) return fail(TARTARUS_E_INVALID, "table needs nr, nth >= 4");
-        if (!finite_pos(m->r_min) || !(m->r_max > m->r_min) || !std::isfinite(m->r_max))
-            return fail(TARTARUS_E_INVALID, "table needs 0 < r_min < r_max");
-        if (precision != TARTARUS_PREC_FP64)
-            return fail(TARTARUS_E_INVALID, "the tabulated metric is traced in FP64 only");
-        if (method != TARTARUS_METHOD_DP45)
-            return fail(TARTARUS_E_INVALID, "the tabulated metric is traced with Dormand-Prince 5(4) only");
-    } else if (m->kind != TARTARUS_METRIC_KERR) {
-        return fail(TARTARUS_E_INVALID, "unknown metric kind");
-    }
-    return TARTARUS_OK;
-}
-
-int check_camera(const tartarus_camera& c, const tartarus_solver* s)
-{
-    if (!finite_pos(c.r_obs)) return fail(TARTARUS_E_INVALID, "r_obs must be > 0");
-    if (!(std::isfinite(c.theta_obs) && c.theta_obs > 0.0 && c.theta_obs < M_PI))
-        return fail(TARTARUS_E_INVALID, "theta_obs must be in (0, pi)");
-    if (c.nx < 1 || c.ny < 1) return fail(TARTARUS_E_INVALID, "nx, ny must be >= 1");
-    const double w[4] = {c.alpha_min, c.alpha_max, c.beta_min, c.beta_max};
-    for (double v : w)
-        if (!std::isfinite(v)) return fail(TARTARUS_E_INVALID, "non-finite image window");
-    const double am = std::max(std::fabs(c.alpha_min), std::fabs(c.alpha_max));
-    const double bm = std::max(std::fabs(c.beta_min), std::fabs(c.beta_max));
-    if (!(am * am + bm * bm < c.r_obs * c.r_obs)) return fail(TARTARUS_E_INVALID, "image window must satisfy alpha^2 + beta^2 < r_obs^2");
-    if (s && !(s->r_escape > c.r_obs)) return fail(TARTARUS_E_INVALID, "r_escape must exceed r_obs");
-    if ((long long)c.nx * c.ny > (1ll << 40)) return fail(TARTARUS_E_INVALID, "image too large");
-    return TARTARUS_OK;
-}
-
-int check_solver(const tartarus_solver* s)
-{
-    if (!s) return fail(TARTARUS_E_INVALID, "solver is NULL");
-    if (!finite_pos(s->rtol)) return fail(TARTARUS_E_INVALID, "rtol must be > 0");
-    if (!finite_pos(s->atol)) return fail(TARTARUS_E_INVALID, "atol must be > 0");
-    if (!finite_pos(s->h0_frac)) return fail(TARTARUS_E_INVALID, "h0_frac must be > 0");
-    if (!(std::isfinite(s->horizon_factor) && s->horizon_factor >= 1.0))
-        return fail(TARTARUS_E_INVALID, "horizon_factor must be >= 1");
-    if (!(finite_pos(s->r_escape) && s->r_escape <= 1e15))
-        return fail(TARTARUS_E_INVALID, "r_escape must be in (0, 1e15]");
-    if (!finite_pos(s->event_tol)) return fail(TARTARUS_E_INVALID, "event_tol must be > 0");
-    if (s->max_steps < 1) return fail(TARTARUS_E_INVALID, "max_steps must be >= 1");
-    if (s->precision != TARTARUS_PREC_FP64 && s->precision != TARTARUS_PREC_MIXED)
-        return fail(TARTARUS_E_INVALID, "unknown precision");
-    if (s->method < TARTARUS_METHOD_DP45 || s->method > TARTARUS_METHOD_VERLET)
-        return fail(TARTARUS_E_INVALID,
-                    "unknown method (0 Dormand-Prince, 1 Cash-Karp, 2 Fehlberg, 3 Gragg-Bulirsch-Stoer, 4 Verlet)");
-    if (s->precision == TARTARUS_PREC_MIXED && s->method != TARTARUS_METHOD_DP45)
-        return fail(TARTARUS_E_INVALID, "mixed precision is provided with Dormand-Prince 5(4) only");
-    return TARTARUS_OK;
-}
-
-int check_disk(const tartarus_disk* d)
-{
-    if (!d) return fail(TARTARUS_E_INVALID, "disk is NULL");
-    if (d->max_hits < 0 || d->max_hits > 3) return fail(TARTARUS_E_INVALID, "max_hits must be in 0..3");
-    if (d->opaque != 0 && d->opaque != 1) return fail(TARTARUS_E_INVALID, "disk opaque must be 0 or 1");
-    if (d->opaque && d->max_hits < 1) return fail(TARTARUS_E_INVALID, "an opaque disk needs max_hits >= 1");
-    if (d->shading != TARTARUS_SHADE_OBSERVED && d->shading != TARTARUS_SHADE_INTRINSIC)
-        return fail(TARTARUS_E_INVALID, "unknown disk shading");
-    if (d->max_hits > 0) {
-        if (!std::isfinite(d->r_in) || !std::isfinite(d->r_out)) return fail(TARTARUS_E_INVALID, "non-finite disk radii");
-        if (!(d->r_out > 0.0)) return fail(TARTARUS_E_INVALID, "disk r_out must be > 0");
-        if (d->r_in > 0.0 && !(d->r_out > d->r_in)) return fail(TARTARUS_E_INVALID, "disk needs r_out > r_in");
-    }
-    return TARTARUS_OK;
-}
-
-int check_outputs(const tartarus_outputs* o)
-{
-    if (!o) return fail(TARTARUS_E_INVALID, "outputs is NULL");
-    const void* p[] = {o->cls, o->n_hits, o->final_rtp, o->h_drift, o->h_gate, o->hit_r, o->hit_g, o->hit_flux,
-                       o->hit_lambda, o->hit_order, o->intensity, o->n_accept, o->n_reject, o->n_fp32, o->n_cross};
-    for (const void* q : p)
-        if (!q) return fail(TARTARUS_E_INVALID, "an output buffer is NULL");
-    return TARTARUS_OK;
-}
-
-int validate_all(const tartarus_metric* metric, const tartarus_camera* cams, int ncams, const tartarus_disk* disk,
-                 const tartarus_solver* solver)
-{
-    int rc;
-    if ((rc = check_solver(solver))) return rc;
-    if ((rc = check_metric(metric, solver->precision, solver->method))) return rc;
-    if ((rc = check_disk(disk))) return rc;
-    if (!cams || ncams < 1) return fail(TARTARUS_E_INVALID, "need at least one camera");
-    for (int c = 0; c < ncams; ++c) {
-        if ((rc = check_camera(cams[c], solver))) return rc;
-        if (cams[c].nx != cams[0].nx || cams[c].ny != cams[0].ny)
-            return fail(TARTARUS_E_INVALID, "all cameras of a trace must share nx, ny");
-    }
-    return TARTARUS_OK;
-}
-
-void fill_job(DevJob& J, const tartarus_metric* m, const tartarus_camera& c, const tartarus_disk* d,
-              const tartarus_solver* s, const tartarus_outputs* o, long long begin, long long offset, double* rec)
-{
-    std::memset(&J, 0, sizeof(J));
-    J.ray_begin = begin;
-    J.ray_count = (long long)c.nx * c.ny;
-    J.nx = c.nx;
-    J.ny = c.ny;
-    J.max_hits = d->max_hits;
-    J.disk_flags = (d->opaque ? DISK_OPAQUE : 0) | (d->shading == TARTARUS_SHADE_INTRINSIC ? DISK_INTRINSIC : 0);
-    J.a = m->a;
-    J.r_obs = c.r_obs;
-    J.theta_obs = c.theta_obs;
-    J.alpha_min = c.alpha_min;
-    J.alpha_max = c.alpha_max;
-    J.beta_min = c.beta_min;
-    J.beta_max = c.beta_max;
-    J.disk_r_in = d->r_in;
-    J.disk_r_out = d->r_out;
-    J.cls = o->cls + offset;
-    J.n_hits = o->n_hits + offset;
-    J.final_rtp = o->final_rtp + 3 * offset;
-    J.h_drift = o->h_drift + offset;
-    J.h_gate = o->h_gate + offset;
-    J.hit_r = o->hit_r + 3 * offset;
-    J.hit_g = o->hit_g + 3 * offset;
-    J.hit_flux = o->hit_flux + 3 * offset;
-    J.hit_lambda = o->hit_lambda + 3 * offset;
-    J.hit_order = o->hit_order + 3 * offset;
-    J.intensity = o->intensity + offset;
-    J.n_accept = o->n_accept + offset;
-    J.n_reject = o->n_reject + offset;
-    J.n_fp32 = o->n_fp32 + offset;
-    J.n_cross = o->n_cross + offset;
-    J.remaining = nullptr;
-    J.rec = rec;
-    J.event_tol = s->event_tol;
-}
-
-void fill_args(LaunchArgs& A, const tartarus_metric* m, const tartarus_solver* s)
-{
-    std::memset(&A, 0, sizeof(A));
-    A.rtol = s->rtol;
-    A.atol = s->atol;
-    A.h0_frac = s->h0_frac;
-    A.event_tol = s->event_tol;
-    A.horizon_factor = s->horizon_factor;
-    A.r_escape = s->r_escape;
-    A.max_steps = s->max_steps;
-    A.r_switch_factor = kDefaultSwitch;
-    A.turn_r = kDefaultTurnR;
-    A.turn_th = kDefaultTurnTh;
-    // experiment overrides of the mixed-precision regime
-    if (const char* e = std::getenv("TARTARUS_MIXED_SWITCH")) {
-        const double v = std::atof(e);
-        if (v > 0.0) A.r_switch_factor = v;
-    }
-    if (const char* e = std::getenv("TARTARUS_MIXED_TURN_R")) A.turn_r = std::atof(e);
-    if (const char* e = std::getenv("TARTARUS_MIXED_TURN_TH")) A.turn_th = std::atof(e);
-    if (m->kind == TARTARUS_METRIC_TABLE) {
-        A.table = m->table;
-        A.nr = m->nr;
-        A.nth = m->nth;
-        A.tab_r_min = m->r_min;
-        A.tab_r_max = m->r_max;
-    }
-}
-
 int tune_key(int kind, int prec, int method) { return (kind * 2 + prec) * 8 + method; }
 
 tartarus_launch default_launch(int kind, int prec, int method)
@@ -343,46 +161,17 @@ tartarus_launch default_launch(int kind, int prec, int method)
     return L;
 }
 
-// Resolve a launch request against the tuned or default shape.  n_rays > 0
-// (a one-shot trace of that many rays) lets an unset blocks_per_cu depend on
-// the size: with few rays per lane the longest rays set the kernel time and a
-// lone wavefront per SIMD runs them fastest; with many, a second wavefront's
-// throughput wins (measured: one block of 256 per CU on a 512^2 image, two on
-// 1024^2 and 2048^2 images).
-constexpr long long kRaysPerLaneForFullOccupancy = 8;
-
-int resolve_launch(int kind, int prec, int method, const tartarus_launch* req_in, tartarus_launch& L, int& grid,
+// Resolve a launch request against the tuned or default shape (the rules are
+// in host_logic.cpp); n_rays > 0 is a one-shot trace of that many rays.  The
+// caller holds g_dev.mu (the tuning table).
+int resolve_launch(int kind, int prec, int method, const tartarus_launch* req, tartarus_launch& L, int& grid,
                    long long n_rays = 0)
 {
-    // req_in may point at L itself: read the request before L is overwritten
-    tartarus_launch req_copy;
-    const tartarus_launch* req = nullptr;
-    if (req_in) {
-        req_copy = *req_in;
-        req = &req_copy;
-    }
-    L = default_launch(kind, prec, method);
-    if (req) {
-        if (req->block_threads > 0) L.block_threads = req->block_threads;
-        if (req->blocks_per_cu > 0) L.blocks_per_cu = req->blocks_per_cu;
-        if (req->chunk > 0) L.chunk = req->chunk;
-        if (req->refill_min > 0) L.refill_min = req->refill_min;
-        if (req->order > 0) L.order = req->order;
-    }
-    if (L.order < 0 || L.order > TARTARUS_ORDER_TILE) return fail(TARTARUS_E_INVALID, "unknown queue order");
-    if (L.block_threads != 64 && L.block_threads != 128 && L.block_threads != 256)
-        return fail(TARTARUS_E_INVALID, "block_threads must be 64, 128 or 256");
-    if (L.refill_min < 1 || L.refill_min > 64) return fail(TARTARUS_E_INVALID, "refill_min must be in 1..64");
-    if (L.chunk < 1) return fail(TARTARUS_E_INVALID, "chunk must be >= 1");
+    int rc = merge_shape(default_launch(kind, prec, method), req, L);
+    if (rc) return rc;
     int occ = 0;
     HIP_TRY(tartarus_occupancy(kind, prec, method, L.block_threads, &occ));
-    if (occ < 1) return fail(TARTARUS_E_DEVICE, "kernel cannot be resident with this block size");
-    if (L.blocks_per_cu <= 0 && n_rays > 0 &&
-        n_rays < kRaysPerLaneForFullOccupancy * (long long)g_dev.cus * L.block_threads)
-        L.blocks_per_cu = 1;
-    if (L.blocks_per_cu <= 0 || L.blocks_per_cu > occ) L.blocks_per_cu = occ;
-    grid = g_dev.cus * L.blocks_per_cu;
-    return TARTARUS_OK;
+    return finish_shape(L, occ, n_rays, g_dev.cus, grid);
 }
 
 // Enqueue one trace (no validation) on the stream.
@@ -493,7 +282,7 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
 // ---------------------------------------------------------------------------
 // exported
 // ---------------------------------------------------------------------------
-extern "C" const char* tartarus_last_error(void) { return g_err.c_str(); }
+extern "C" const char* tartarus_last_error(void) { return last_error(); }
 
 extern "C" int tartarus_validate(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
                                  const tartarus_disk* disk, const tartarus_solver* solver)
@@ -548,7 +337,7 @@ extern "C" int tartarus_build_kerr_table(double a, int nr, int nth, double r_min
 {
     if (!(std::isfinite(a) && a >= 0.0 && a < 1.0)) return fail(TARTARUS_E_INVALID, "spin a must be in [0, 1)");
     if (nr < 4 || nth < 4) return fail(TARTARUS_E_INVALID, "table needs nr, nth >= 4");
-    if (!finite_pos(r_min) || !(r_max > r_min) || !std::isfinite(r_max))
+    if (!(std::isfinite(r_min) && r_min > 0.0) || !(r_max > r_min) || !std::isfinite(r_max))
         return fail(TARTARUS_E_INVALID, "table needs 0 < r_min < r_max");
     if (!table) return fail(TARTARUS_E_INVALID, "table is NULL");
     std::lock_guard<std::mutex> lk(g_dev.mu);
@@ -748,14 +537,6 @@ int64_t now_ns()
         .count();
 }
 
-size_t output_bytes_per_ray()
-{
-    // cls, n_hits, n_accept, n_reject, n_fp32, n_cross (int32); final_rtp[3], h_drift,
-    // h_gate, intensity (double); hit_r, hit_g, hit_flux, hit_lambda [3] (double); hit_order[3] (int32);
-    // the ray's record for the finishing pass
-    return 6 * 4 + 6 * 8 + 12 * 8 + 3 * 4 + REC_DOUBLES * sizeof(double);
-}
-
 struct Request {
     tartarus_metric metric;
     tartarus_camera cam;
@@ -763,7 +544,7 @@ struct Request {
     tartarus_solver solver;
     tartarus_outputs out;
     long long nrays = 0;
-    size_t bytes = 0;
+    size_t held = 0;        // device bytes counted against the budget while admitted
     int state = 0;          // 0 queued, 1 running, 2 done
     int entry = -1;
     long long ray_begin = 0;
@@ -815,51 +596,24 @@ struct Server {
     int grid = 0, block = 0;
     size_t arena_bytes = 0;
     // freed per-request record buffers kept for reuse (hipFree would
-    // synchronize the device between epochs): size in rays -> buffers
-    std::multimap<long long, double*> rec_pool;
-    size_t rec_pool_bytes = 0;
+    // synchronize the device between epochs), counted against the budget
+    RecordPool rec_pool;
     std::string dev_error;
 };
 Server g_srv;
 
-// A record buffer for n rays: the smallest pooled one that fits, else a new one.
-double* rec_take(Server& S, long long n, long long& cap)
+// Free every pooled record buffer (hipFree synchronizes the device; done only
+// when admission needs the memory).
+void rec_pool_release(Server& S)
 {
-    auto it = S.rec_pool.lower_bound(n);
-    if (it != S.rec_pool.end() && it->first <= 4 * n) {
-        double* p = it->second;
-        cap = it->first;
-        S.rec_pool_bytes -= (size_t)it->first * REC_DOUBLES * sizeof(double);
-        S.rec_pool.erase(it);
-        return p;
-    }
-    double* p = nullptr;
-    if (hipMalloc(&p, (size_t)n * REC_DOUBLES * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        // release the pool and try once more
-        for (auto& kv : S.rec_pool) (void)hipFree(kv.second);
-        S.rec_pool.clear();
-        S.rec_pool_bytes = 0;
-        if (hipMalloc(&p, (size_t)n * REC_DOUBLES * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-    }
-    cap = n;
-    return p;
+    for (void* p : S.rec_pool.drain()) (void)hipFree(p);
 }
 
-// Return a buffer of n rays to the pool (kept while the pool stays under a
-// quarter of the HBM budget, else freed).
-void rec_give(Server& S, double* p, long long n)
+// Return a request's record buffer to the pool (kept while the pool stays under
+// a quarter of the HBM budget, else freed).
+void rec_give(Server& S, double* p, long long cap)
 {
-    const size_t b = (size_t)n * REC_DOUBLES * sizeof(double);
-    if (S.rec_pool_bytes + b <= g_dev.budget / 4) {
-        S.rec_pool.emplace(n, p);
-        S.rec_pool_bytes += b;
-    } else {
-        (void)hipFree(p);
-    }
+    if (!S.rec_pool.give(p, cap, g_dev.budget / 4)) (void)hipFree(p);
 }
 
 int server_alloc(int prec, int method)
@@ -869,8 +623,12 @@ int server_alloc(int prec, int method)
     HIP_TRY(hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
     tartarus_launch L;
     int grid = 0;
-    int rc = resolve_launch(TARTARUS_METRIC_KERR, prec, method, nullptr, L, grid);
-    if (rc) return rc;
+    {
+        // the tuning table is shared with tartarus_autotune
+        std::lock_guard<std::mutex> dlk(g_dev.mu);
+        int rc = resolve_launch(TARTARUS_METRIC_KERR, prec, method, nullptr, L, grid);
+        if (rc) return rc;
+    }
     S.grid = grid;
     S.block = L.block_threads;
     S.nslots = (long long)grid * L.block_threads;
@@ -920,9 +678,7 @@ void server_free()
     (void)hipHostFree(S.hseg_ray);
     (void)hipFree(S.slots);
     (void)hipFree(S.slot_live);
-    for (auto& kv : S.rec_pool) (void)hipFree(kv.second);
-    S.rec_pool.clear();
-    S.rec_pool_bytes = 0;
+    rec_pool_release(S);
     (void)hipFree(S.dhead);
     (void)hipHostFree(S.hhead);
     if (S.stream) (void)hipStreamDestroy(S.stream);
@@ -948,7 +704,8 @@ void finish_request(Server& S, uint64_t ticket, Request& R)
         S.entry_ticket[R.entry] = 0;
         S.hjobs[R.entry].cancelled = 0;
         R.entry = -1;
-        S.used_bytes -= R.bytes;
+        S.used_bytes -= R.held;
+        R.held = 0;
     }
     if (R.rec) {
         rec_give(S, R.rec, R.rec_rays);
@@ -966,7 +723,7 @@ int server_round(std::unique_lock<std::mutex>& lk)
     while (!S.queue.empty()) {
         const uint64_t t = S.queue.front();
         Request& R = S.reqs[t];
-        if (R.bytes + S.arena_bytes > g_dev.budget) {
+        if (never_fits(R.nrays, S.arena_bytes, g_dev.budget)) {
             // submit checked against an estimate of the arena; this one never fits
             S.queue.pop_front();
             R.too_large = true;
@@ -977,8 +734,28 @@ int server_round(std::unique_lock<std::mutex>& lk)
         int entry = -1;
         for (int e = 0; e < kMaxEntries; ++e)
             if (!S.entry_ticket[e]) { entry = e; break; }
-        if (entry < 0 || S.used_bytes + R.bytes + S.arena_bytes > g_dev.budget) break;
-        R.rec = rec_take(S, R.nrays, R.rec_rays);
+        if (entry < 0) break;
+        // records: a pooled buffer of n..4n rays if there is one, else a new one
+        // of n; the pool's buffers count against the budget, and are released
+        // when the request would fit without them
+        long long cap = S.rec_pool.pooled_capacity(R.nrays);
+        bool pooled = cap > 0;
+        if (!pooled) cap = R.nrays;
+        if (!admission_fits(S.used_bytes, S.rec_pool.bytes(), S.arena_bytes, g_dev.budget, R.nrays, cap, pooled)) {
+            if (S.rec_pool.empty() ||
+                !admission_fits(S.used_bytes, 0, S.arena_bytes, g_dev.budget, R.nrays, R.nrays, false))
+                break;   // waits for running requests to release memory
+            rec_pool_release(S);
+            pooled = false;
+            cap = R.nrays;
+        }
+        if (pooled) {
+            R.rec = (double*)S.rec_pool.take_pooled(R.nrays, cap);
+        } else if (hipMalloc(&R.rec, (size_t)cap * kRecordBytes) != hipSuccess) {
+            (void)hipGetLastError();
+            R.rec = nullptr;
+        }
+        R.rec_rays = cap;
         if (!R.rec) {
             if (any_live(S)) break;   // retried once running requests have released memory
             S.queue.pop_front();      // nothing else holds device memory: it never fits
@@ -991,7 +768,8 @@ int server_round(std::unique_lock<std::mutex>& lk)
         R.entry = entry;
         R.ray_begin = S.next_ray;
         S.next_ray += R.nrays;
-        S.used_bytes += R.bytes;
+        R.held = held_bytes(R.nrays, R.rec_rays);
+        S.used_bytes += R.held;
         R.state = 1;
         R.t_admit = now_ns();
         S.entry_ticket[entry] = t;
@@ -1026,26 +804,21 @@ int server_round(std::unique_lock<std::mutex>& lk)
     }
     if (nd == 0) return TARTARUS_OK;
     // ---- this epoch's queue: the unstarted rays of every live request, one
-    // segment each, fewest unstarted rays first (or in arrival order);
-    // cancelled requests go first so that their rays drain at once
-    std::vector<std::tuple<int, long long, long long, int>> segs;   // (class, key, ray_begin, entry)
+    // segment each (ordering rules in host_logic.cpp)
+    std::vector<SegmentSource> live;
     for (int e = 0; e < kMaxEntries; ++e) {
         const uint64_t t = S.entry_ticket[e];
         if (!t) continue;
         const Request& R = S.reqs[t];
-        if (R.started >= R.nrays) continue;
-        const long long key = S.serve_order == TARTARUS_SERVE_SMALLEST_FIRST ? R.nrays - R.started : R.ray_begin;
-        segs.push_back({S.hjobs[e].cancelled ? 0 : 1, key, R.ray_begin, e});
+        live.push_back({e, S.hjobs[e].cancelled, R.nrays, R.started, R.ray_begin});
     }
-    std::sort(segs.begin(), segs.end());
-    const int nseg = (int)segs.size();
+    const std::vector<Segment> segv = build_segments(live, S.serve_order);
+    const int nseg = (int)segv.size();
     S.hseg_q[0] = 0;
     for (int k = 0; k < nseg; ++k) {
-        const int e = std::get<3>(segs[k]);
-        const Request& R = S.reqs[S.entry_ticket[e]];
-        S.seg_entry[k] = e;
-        S.hseg_ray[k] = R.ray_begin + R.started;
-        S.hseg_q[k + 1] = S.hseg_q[k] + (R.nrays - R.started);
+        S.seg_entry[k] = segv[k].entry;
+        S.hseg_ray[k] = segv[k].ray;
+        S.hseg_q[k + 1] = segv[k].q_begin + segv[k].count;
     }
     const long long total = S.hseg_q[nseg];
     const tartarus_solver sv = S.solver;
@@ -1102,13 +875,8 @@ int server_round(std::unique_lock<std::mutex>& lk)
 
     lk.lock();
     // the queue was consumed in segment order
-    long long taken = std::min((long long)*S.hhead, total);
-    for (int k = 0; k < nseg && taken > 0; ++k) {
-        Request& R = S.reqs[S.entry_ticket[S.seg_entry[k]]];
-        const long long c = std::min(taken, R.nrays - R.started);
-        R.started += c;
-        taken -= c;
-    }
+    const std::vector<long long> used = consumed_per_segment(segv, std::min((long long)*S.hhead, total));
+    for (int k = 0; k < nseg; ++k) S.reqs[S.entry_ticket[S.seg_entry[k]]].started += used[k];
     for (int e : done) {
         const uint64_t t = S.entry_ticket[e];
         finish_request(S, t, S.reqs[t]);
@@ -1186,10 +954,9 @@ extern "C" int tartarus_submit(const tartarus_metric* metric, const tartarus_cam
     R.solver = *solver;
     R.out = *out;
     R.nrays = (long long)cam->nx * cam->ny;
-    R.bytes = (size_t)R.nrays * output_bytes_per_ray();
     // the slot arena is allocated when the scheduler starts; estimate it beforehand
     const size_t arena = S.dev_ready ? S.arena_bytes : (size_t)g_dev.cus * 768 * (SLOT_DOUBLES * 8 + 4);
-    if (R.bytes + arena > g_dev.budget)
+    if (never_fits(R.nrays, arena, g_dev.budget))
         return fail(TARTARUS_E_TOO_LARGE, "request needs more than the HBM budget");
     if (R.nrays > 0xffffffffll) return fail(TARTARUS_E_TOO_LARGE, "request has too many rays");
     R.t_submit = now_ns();

@@ -539,18 +539,38 @@ __device__ __forceinline__ void disk_crossing(Ray& R, double h, const Deriv<doub
 // The regime is decided per ray from its own state only (never from its
 // wavefront), so a ray's arithmetic is the same in any batch.  FP32 stages are
 // used where r >= r_switch_factor * r_+ at the start of the step, away from
-// radial and polar turning points, away from the polar axis, and not right
-// after a rejected attempt.  Near the axis sin(theta) is small and p_phi /
-// sin^2(theta) large, and theta rounded to FP32 leaves sin^2(theta) with a
-// relative error of order 1e-7 / sin(theta): the FP32 error estimate of p_theta
-// then sits above the tolerance and the step collapses (rays of zero angular
-// momentum cross the axis; |cos(theta)| <= 0.995 keeps them in FP64 there).  A
-// rejection is retried with FP64 stages instead of shrinking the step on FP32
-// rounding noise.
+// radial and polar turning points, away from the polar axis, and where the
+// FP32 rounding of the error estimate stays well below the tolerance.  Near
+// the axis sin(theta) is small and p_phi / sin^2(theta) large, and theta
+// rounded to FP32 leaves sin^2(theta) with a relative error of order
+// 1e-7 / sin(theta): the FP32 error estimate of p_theta then sits above the
+// tolerance and the step collapses (rays of zero angular momentum cross the
+// axis; |cos(theta)| <= 0.995 keeps them in FP64 there).
+//
+// Noise floor: a stage slope evaluated in FP32 carries a relative error of a
+// few FP32 ulps, so the estimate h sum_j e_j k_j of component i carries about
+// |e|_2 * 4 * 2^-24 * h |k_i| of rounding (|e|_2 = 0.0798 for the
+// Dormand-Prince error weights).  FP32 stages are used only where that is at
+// most half of the component's tolerance scale atol + rtol |y_i|, i.e.
+// h |k_i| <= kNoiseRatio (atol + rtol |y_i|); otherwise an FP32 attempt would
+// be rejected on rounding noise and the step driven down to the noise level.
+// The same bound keeps the FP32 rounding of the state update below the
+// tolerance.  At tight tolerances the test leaves FP32 off almost everywhere.
+constexpr double kDp45ErrNorm = 0.07976;                          // |b - b*|_2
+constexpr double kNoiseRatio = 0.5 / (kDp45ErrNorm * 4.0 * 0x1p-24);   // ~2.6e7
+
+__device__ __forceinline__ bool fp32_noise_ok(double hk, double y, double atol, double rtol)
+{
+    return fabs(hk) <= kNoiseRatio * fma(rtol, fabs(y), atol);
+}
+
 __device__ __forceinline__ bool far_field(const Ray& R, const LaunchArgs& A)
 {
-    return !R.rej_prev && R.r >= A.r_switch_factor * R.rp && R.cth * R.cth <= 0.99 &&
-           fabs(R.pr) >= (double)R.guard_r && fabs(R.pth) >= (double)R.guard_th;
+    const double h = R.h, atol = A.atol, rtol = A.rtol;
+    return R.r >= A.r_switch_factor * R.rp && R.cth * R.cth <= 0.99 && fabs(R.pr) >= (double)R.guard_r &&
+           fabs(R.pth) >= (double)R.guard_th && fp32_noise_ok(h * R.k.r, R.r, atol, rtol) &&
+           fp32_noise_ok(h * R.k.th, R.th, atol, rtol) && fp32_noise_ok(h * R.k.ph, R.ph, atol, rtol) &&
+           fp32_noise_ok(h * R.k.pr, R.pr, atol, rtol) && fp32_noise_ok(h * R.k.pth, R.pth, atol, rtol);
 }
 
 // One attempted DP45 step whose six new stage evaluations run in FP32 (on-shell
@@ -835,46 +855,71 @@ constexpr GbsWeights make_gbs_weights()
 
 __constant__ GbsWeights kGbsW = make_gbs_weights();
 
+// Rounding floor of the extrapolation's error estimate: a component whose
+// estimate is at most kGbsFloorUlps ulps of the largest increment of that
+// component among the sweeps, capped at kGbsFloorTol of its tolerance scale,
+// counts as zero.  Far from the hole the truncation error of a macro-step lies
+// below the rounding of T[K-1][K-1] - T[K-1][K-2]; a step factor taken from
+// that noise would differ between any two correct FP64 evaluations.  The
+// threshold sits far above the noise (tens of ulps), so both fall on the same
+// side of it; the cap keeps the tolerance's meaning at tight tolerances.
+constexpr double kGbsFloorUlps = 262144.0;   // 2^18
+constexpr double kGbsFloorTol = 0.01;
+
+__device__ __forceinline__ double gbs_floor(double e, double big, double y0, double y1, double atol, double rtol)
+{
+    const double fl = fmin(kGbsFloorUlps * 0x1p-52 * big, kGbsFloorTol * fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
+    return fabs(e) <= fl ? 0.0 : e;
+}
+
 // One macro-step of the extrapolation with FP64 stages: the same outputs as
-// stages64 (y5 = T[K-1][K-1], k7 = f(y5), H(y5), cos(theta5), error vector).
+// stages64 (y5 = y + T[K-1][K-1], k7 = f(y5), H(y5), cos(theta5), error
+// vector with the rounding floor for (atol, rtol); atol = rtol = 0: none).
+// The sweeps and the tableau carry increments z - y (the extrapolation is
+// linear, so this is the same scheme), which keeps the rounding of the
+// estimate at the size of the step's change instead of the state's.
 // The row and substep loops are uniform across the wavefront (every lane runs
 // the same substep counts), so one inlined right-hand side serves all 42
 // substep evaluations.  Rows are folded into the tableau in place, all
 // kGbsColumns entries per row: entries past the row's own take a zero weight
 // and copy their left neighbour, so register indices stay compile-time.
 template <int KIND>
-__device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
-                                             Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
+__device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>& M, double h, double atol,
+                                             double rtol, Deriv<double>& y5, Deriv<double>& k7, Deriv<double>& e,
+                                             double& H5, double& c5)
 {
     constexpr int K = kGbsColumns;
     const double a = R.a;
     double Tt[K], Tr[K], Tth[K], Tph[K], Tpr[K], Tpth[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) Tt[k] = Tr[k] = Tth[k] = Tph[k] = Tpr[k] = Tpth[k] = 0.0;
+    double bt = 0.0, br = 0.0, bth = 0.0, bph = 0.0, bpr = 0.0, bpth = 0.0;   // largest |sweep increment|
 #pragma unroll 1
     for (int i = 0; i < K; ++i) {
         const int n = 2 * (i + 1);
         const double hs = h / (double)n;
         const double h2 = 2.0 * hs;
-        // z_0 = y, z_1 = y + hs f(y)
-        double pt_ = R.t, pr_ = R.r, pth_ = R.th, pph_ = R.ph, ppr_ = R.pr, ppth_ = R.pth;
-        double zt = fma(hs, R.k.t, R.t), zr = fma(hs, R.k.r, R.r), zth = fma(hs, R.k.th, R.th);
-        double zph = fma(hs, R.k.ph, R.ph), zpr = fma(hs, R.k.pr, R.pr), zpth = fma(hs, R.k.pth, R.pth);
+        // d_0 = 0, d_1 = hs f(y)
+        double pt_ = 0.0, pr_ = 0.0, pth_ = 0.0, pph_ = 0.0, ppr_ = 0.0, ppth_ = 0.0;
+        double dt = hs * R.k.t, dr = hs * R.k.r, dth = hs * R.k.th;
+        double dph = hs * R.k.ph, dpr = hs * R.k.pr, dpth = hs * R.k.pth;
         Deriv<double> dz;
         for (int m = 1;; ++m) {
             double Hd, cd;
-            M.rhs(a, zr, zth, zpr, zpth, R.pt, R.pph, dz, Hd, cd);
+            M.rhs(a, R.r + dr, R.th + dth, R.pr + dpr, R.pth + dpth, R.pt, R.pph, dz, Hd, cd);
             if (m == n) break;
-            // z_{m+1} = z_{m-1} + 2 hs f(z_m)
+            // d_{m+1} = d_{m-1} + 2 hs f(y + d_m)
             const double nt = fma(h2, dz.t, pt_), nr = fma(h2, dz.r, pr_), nth = fma(h2, dz.th, pth_);
             const double nph = fma(h2, dz.ph, pph_), npr = fma(h2, dz.pr, ppr_), npth = fma(h2, dz.pth, ppth_);
-            pt_ = zt; pr_ = zr; pth_ = zth; pph_ = zph; ppr_ = zpr; ppth_ = zpth;
-            zt = nt; zr = nr; zth = nth; zph = nph; zpr = npr; zpth = npth;
+            pt_ = dt; pr_ = dr; pth_ = dth; pph_ = dph; ppr_ = dpr; ppth_ = dpth;
+            dt = nt; dr = nr; dth = nth; dph = nph; dpr = npr; dpth = npth;
         }
-        // smoothing: (z_n + z_{n-1} + hs f(z_n)) / 2
-        double vt = 0.5 * (pt_ + fma(hs, dz.t, zt)), vr = 0.5 * (pr_ + fma(hs, dz.r, zr));
-        double vth = 0.5 * (pth_ + fma(hs, dz.th, zth)), vph = 0.5 * (pph_ + fma(hs, dz.ph, zph));
-        double vpr = 0.5 * (ppr_ + fma(hs, dz.pr, zpr)), vpth = 0.5 * (ppth_ + fma(hs, dz.pth, zpth));
+        // smoothing: (d_n + d_{n-1} + hs f(y + d_n)) / 2
+        double vt = 0.5 * (pt_ + fma(hs, dz.t, dt)), vr = 0.5 * (pr_ + fma(hs, dz.r, dr));
+        double vth = 0.5 * (pth_ + fma(hs, dz.th, dth)), vph = 0.5 * (pph_ + fma(hs, dz.ph, dph));
+        double vpr = 0.5 * (ppr_ + fma(hs, dz.pr, dpr)), vpth = 0.5 * (ppth_ + fma(hs, dz.pth, dpth));
+        bt = fmax(bt, fabs(vt)); br = fmax(br, fabs(vr)); bth = fmax(bth, fabs(vth));
+        bph = fmax(bph, fabs(vph)); bpr = fmax(bpr, fabs(vpr)); bpth = fmax(bpth, fabs(vpth));
         // fold into the tableau
 #pragma unroll
         for (int k = 0; k < K - 1; ++k) {
@@ -887,19 +932,32 @@ __device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>
         }
         Tt[K - 1] = vt; Tr[K - 1] = vr; Tth[K - 1] = vth; Tph[K - 1] = vph; Tpr[K - 1] = vpr; Tpth[K - 1] = vpth;
     }
-    y5.t = Tt[K - 1];
-    y5.r = Tr[K - 1];
-    y5.th = Tth[K - 1];
-    y5.ph = Tph[K - 1];
-    y5.pr = Tpr[K - 1];
-    y5.pth = Tpth[K - 1];
-    e.t = Tt[K - 1] - Tt[K - 2];
-    e.r = Tr[K - 1] - Tr[K - 2];
-    e.th = Tth[K - 1] - Tth[K - 2];
-    e.ph = Tph[K - 1] - Tph[K - 2];
-    e.pr = Tpr[K - 1] - Tpr[K - 2];
-    e.pth = Tpth[K - 1] - Tpth[K - 2];
+    y5.t = R.t + Tt[K - 1];
+    y5.r = R.r + Tr[K - 1];
+    y5.th = R.th + Tth[K - 1];
+    y5.ph = R.ph + Tph[K - 1];
+    y5.pr = R.pr + Tpr[K - 1];
+    y5.pth = R.pth + Tpth[K - 1];
+    e.t = gbs_floor(Tt[K - 1] - Tt[K - 2], bt, R.t, y5.t, atol, rtol);
+    e.r = gbs_floor(Tr[K - 1] - Tr[K - 2], br, R.r, y5.r, atol, rtol);
+    e.th = gbs_floor(Tth[K - 1] - Tth[K - 2], bth, R.th, y5.th, atol, rtol);
+    e.ph = gbs_floor(Tph[K - 1] - Tph[K - 2], bph, R.ph, y5.ph, atol, rtol);
+    e.pr = gbs_floor(Tpr[K - 1] - Tpr[K - 2], bpr, R.pr, y5.pr, atol, rtol);
+    e.pth = gbs_floor(Tpth[K - 1] - Tpth[K - 2], bpth, R.pth, y5.pth, atol, rtol);
     M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+}
+
+// The extrapolation's own solution at lambda + sh: one macro-step of length sh
+// from the ray's state (no error control), and the slope there.  Event roots
+// of the extrapolation are located on it: a macro-step spans up to hundreds of
+// M, over which the cubic Hermite interpolant is accurate to ~1e-3 only.
+template <int KIND>
+__device__ __forceinline__ void gbs_point(const Ray& R, const MetricOps<KIND>& M, double sh, Deriv<double>& y,
+                                       Deriv<double>& k)
+{
+    Deriv<double> e;
+    double H, c;
+    stages64_gbs<KIND>(R, M, sh, 0.0, 0.0, y, k, e, H, c);
 }
 
 // Verlet (Sec. 3.2): a fixed step of the generalized Stormer-Verlet scheme for
@@ -977,6 +1035,41 @@ __device__ __forceinline__ double sq_ratio(double e, double y0, double y1, doubl
     return z * z;
 }
 
+// Rounding floor of an embedded pair's error estimate.  The estimate
+// h sum_j (b_j - b*_j) k_j of a component rounds to a few ulps of
+// h |b - b*|_1 max(|k_n|, |k_n+1|); far from the hole the first steps'
+// estimates are that rounding alone (a ~1e9-fold cancellation in the angular
+// components), and a step factor taken from them differs between two correct
+// FP64 evaluations by ~1e-7, enough for a later estimate to fall on the other
+// side of 1.  A component whose estimate is at most kPairFloorUlps of that
+// scale, capped at kPairFloorTol of its tolerance scale, counts as zero.
+constexpr double kPairFloorUlps = 262144.0;   // 2^18
+constexpr double kPairFloorTol = 0.01;
+
+template <int M>
+struct PairErrNorm1;
+template <>
+struct PairErrNorm1<METHOD_DP45> {
+    static constexpr double value = E1 - E3 + E4 - E5 + E6 - E7;   // |b - b*|_1
+};
+template <int M>
+struct PairErrNorm1 {
+    static constexpr double sum(int j) { return j == 6 ? 0.0 : (Pair<M>::e[j] < 0 ? -Pair<M>::e[j] : Pair<M>::e[j]) + sum(j + 1); }
+    static constexpr double value = sum(0);
+};
+
+// Squared scaled error of one component, with the rounding floor: zero when
+// |e| <= min(c max(|k0|, |k1|), kPairFloorTol sc), c = kPairFloorUlps ulp
+// |b - b*|_1 |h|.
+__device__ __forceinline__ double sq_ratio_floor(double e, double c, double k0, double k1, double y0, double y1,
+                                                 double atol, double rtol)
+{
+    const double sc = fma(rtol, fmax(fabs(y0), fabs(y1)), atol);
+    const double fl = fmin(c * fmax(fabs(k0), fabs(k1)), kPairFloorTol * sc);
+    const double z = fabs(e) <= fl ? 0.0 : e * rcp64_coarse(sc);
+    return z * z;
+}
+
 // y^N for a compile-time N >= 1 by repeated squaring.
 template <int N>
 __device__ __forceinline__ double ipow(double y)
@@ -1019,6 +1112,96 @@ __device__ __forceinline__ double step_factor(double err2, double fmx)
     return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<2 * P>(err2)));
 }
 
+// Root in (0, 1] of an event on the extrapolation's own solution over the
+// accepted macro-step [lam, lam + h]: of cos(theta) (disk) or of r - target
+// (radial).  Newton's method on g(s) = event(Phi(s h)), with the slope from
+// f at Phi(s h), starting from the root s0 of the step's cubic; the bracket
+// [lo, hi] keeps the start side at lo, and a Newton step leaving it bisects.
+// Stops when the Newton correction or the bracket is at most tol in lambda;
+// returns the last evaluated point, within tol of the root, with its state in
+// y.  At most 64 iterations.
+template <int KIND>
+__device__ double gbs_root(const Ray& R, const MetricOps<KIND>& M, double h, bool disk, double target, double s0,
+                           double tol, Deriv<double>& y)
+{
+    const bool above = disk ? R.cth > 0.0 : R.r - target > 0.0;
+    double lo = 0.0, hi = 1.0;
+    double s = (s0 > 0.0 && s0 <= 1.0) ? s0 : 0.5;
+    for (int it = 0; it < 64; ++it) {
+        Deriv<double> k;
+        gbs_point<KIND>(R, M, s * h, y, k);
+        double g, dg;
+        if (disk) {
+            double sn, cs;
+            sincos64(y.th, &sn, &cs);
+            g = cs;
+            dg = -sn * k.th * h;
+        } else {
+            g = y.r - target;
+            dg = k.r * h;
+        }
+        if (above ? g > 0.0 : g < 0.0)
+            lo = s;
+        else
+            hi = s;
+        double sn = s - g / dg;
+        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);   // also a zero or non-finite slope
+        if (fabs(sn - s) * h <= tol || (hi - lo) * h <= tol) break;
+        s = sn;
+    }
+    return s;
+}
+
+// Events of an accepted macro-step of the extrapolation, located on its own
+// solution and taken in root order (a disk crossing at or before the terminal
+// root counts, one after it does not); the located hits and the terminal point
+// go to the record as final values.  Returns true when the ray has ended.
+template <int KIND>
+__device__ bool gbs_events(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M, double h,
+                           const Deriv<double>& y5, const Deriv<double>& k7, bool hz, bool es, bool dk,
+                           double target)
+{
+    const double tol = 0.125 * A.event_tol;
+    const Cubic pr(R.r, R.k.r, y5.r, k7.r, h);
+    const Cubic pth(R.th, R.k.th, y5.th, k7.th, h);
+    const bool term = hz | es;
+    Deriv<double> yt, yd;
+    double st = 2.0, sd = 2.0;
+    if (term) st = gbs_root<KIND>(R, M, h, false, target, locate_root(pr, target, hz, h, 1e-6 * h), tol, yt);
+    if (dk) sd = gbs_root<KIND>(R, M, h, true, 0.0, equator_root(pth, R.th, y5.th, R.cth, h, 1e-6 * h), tol, yd);
+    int cls = hz ? CLS_CAPTURED : CLS_ESCAPED;
+    if (dk && sd <= st) {
+        R.n_cross++;
+        const double rr = yd.r;
+        if (rr >= R.r_in && rr <= R.r_out && R.n_hits < R.max_hits) {
+            double* sl = R.rec + REC_SLOT_LEN * R.n_hits;
+            sl[0] = rr;
+            sl[8] = 0.0;
+            sl[9] = fma(sd, h, R.lam);
+            reinterpret_cast<int*>(R.rec + REC_INTS)[6 + R.n_hits] = R.n_cross;
+            R.n_hits++;
+            if (R.opaque) {
+                yt = yd;
+                cls = CLS_ON_DISK;
+            }
+        }
+    }
+    if (!term && cls != CLS_ON_DISK) return false;
+    R.rec[REC_TERM + 0] = yt.r;
+    R.rec[REC_TERM + 4] = yt.th;
+    R.rec[REC_TERM + 8] = yt.ph;
+    ray_finish(R, A, cls, 0);
+    return true;
+}
+
+// The largest power of two not above x (x > 0, finite): the extrapolation's
+// step factor, so its steps stay h0 2^k and an estimate's rounding moves them
+// only where it straddles a power-of-two boundary of the factor.
+__device__ __forceinline__ double pow2_floor(double x)
+{
+    return __longlong_as_double(__double_as_longlong(x) & (long long)0xfff0000000000000ull);
+}
+
 // One attempt; returns true when the ray has terminated (outputs written).
 template <int KIND, int PREC, int METHOD>
 __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
@@ -1052,18 +1235,30 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
             if constexpr (METHOD == METHOD_DP45)
                 stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
             else if constexpr (METHOD == METHOD_GBS)
-                stages64_gbs<KIND>(R, M, h, y5, k7, e, H5, c5);
+                stages64_gbs<KIND>(R, M, h, A.atol, A.rtol, y5, k7, e, H5, c5);
             else
                 stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
         }
         R.n_f32 += used32 ? 1 : 0;
         const double atol = A.atol, rtol = A.rtol;
-        double acc = sq_ratio(e.t, R.t, y5.t, atol, rtol);
-        acc += sq_ratio(e.r, R.r, y5.r, atol, rtol);
-        acc += sq_ratio(e.th, R.th, y5.th, atol, rtol);
-        acc += sq_ratio(e.ph, R.ph, y5.ph, atol, rtol);
-        acc += sq_ratio(e.pr, R.pr, y5.pr, atol, rtol);
-        acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
+        double acc;
+        if constexpr (METHOD == METHOD_GBS) {
+            // (the extrapolation applies its own floor in stages64_gbs)
+            acc = sq_ratio(e.t, R.t, y5.t, atol, rtol);
+            acc += sq_ratio(e.r, R.r, y5.r, atol, rtol);
+            acc += sq_ratio(e.th, R.th, y5.th, atol, rtol);
+            acc += sq_ratio(e.ph, R.ph, y5.ph, atol, rtol);
+            acc += sq_ratio(e.pr, R.pr, y5.pr, atol, rtol);
+            acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
+        } else {
+            const double c = kPairFloorUlps * 0x1p-52 * PairErrNorm1<METHOD>::value * fabs(h);
+            acc = sq_ratio_floor(e.t, c, R.k.t, k7.t, R.t, y5.t, atol, rtol);
+            acc += sq_ratio_floor(e.r, c, R.k.r, k7.r, R.r, y5.r, atol, rtol);
+            acc += sq_ratio_floor(e.th, c, R.k.th, k7.th, R.th, y5.th, atol, rtol);
+            acc += sq_ratio_floor(e.ph, c, R.k.ph, k7.ph, R.ph, y5.ph, atol, rtol);
+            acc += sq_ratio_floor(e.pr, c, R.k.pr, k7.pr, R.pr, y5.pr, atol, rtol);
+            acc += sq_ratio_floor(e.pth, c, R.k.pth, k7.pth, R.pth, y5.pth, atol, rtol);
+        }
         // p_t and p_phi have zero error (their derivatives vanish identically)
         const double err2 = acc * 0.125;   // squared RMS error over the 8 components
         // elementary controller, evaluated once for both outcomes: after a
@@ -1071,6 +1266,7 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
         const bool ok = err2 <= 1.0;
         constexpr int P = METHOD == METHOD_GBS ? 2 * kGbsColumns - 1 : 5;
         fac = isnan(err2) ? 0.2 : step_factor<P>(err2, (ok && !R.rej_prev) ? 10.0 : 1.0);
+        if constexpr (METHOD == METHOD_GBS) fac = pow2_floor(fac);
         if (!ok) {
             // rejected; a NaN or infinite error also lands here
             R.n_rej++;
@@ -1102,7 +1298,9 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     const bool hz = (R.r - r_stop > 0.0) && (y5.r - r_stop <= 0.0);
     const bool es = (R.r - r_esc < 0.0) && (y5.r - r_esc >= 0.0);
     const bool dk = R.max_hits > 0 && ((R.cth > 0.0 && c5 <= 0.0) || (R.cth < 0.0 && c5 >= 0.0));
-    if (hz | es) {
+    if constexpr (METHOD == METHOD_GBS) {
+        if ((hz | es | dk) && gbs_events<KIND>(R, A, M, h, y5, k7, hz, es, dk, hz ? r_stop : r_esc)) return true;
+    } else if (hz | es) {
         // terminal step: the finishing pass locates the root (and a crossing
         // of the equator before it) on the step's cubics; at most one radial
         // event brackets a root in one step
@@ -1110,7 +1308,7 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
         ray_finish(R, A, hz ? CLS_CAPTURED : CLS_ESCAPED, (hz ? 1 : 2) | (dk ? 4 : 0));
         return true;
     }
-    if (dk) {
+    if (METHOD != METHOD_GBS && dk) {
         if (R.opaque) {
             if (opaque_hit(R, h, y5, k7, 0.125 * A.event_tol)) {
                 terminal_step(R, h, y5, k7, 0.0);

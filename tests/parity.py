@@ -7,8 +7,9 @@ image-order boundaries).  Values, on pixels whose classes match and that lie
 outside E: relative error of r_em and g of every recorded hit, of the final
 theta, absolute error of the final phi scaled by max(1, |phi|), and the flux as
 max |dI| / max(I); the constraint residual separately (gated maximum absolute,
-full maximum relative on escaped rays: both depend on the step sequence,
-which two correct implementations reproduce to ~1e-7 relative).
+full maximum on escaped rays within 1e-12 absolute or 1e-4 relative: both
+depend on the step sequence, which two correct implementations reproduce to
+rounding, and the full maximum on the 1/Delta growth of dH/dq near the stop).
 """
 import numpy as np
 
@@ -60,8 +61,12 @@ def compare(g, o, band, tol, h_tol=None):
     errs["h_gate_abs"] = np.abs(g["h_gate"][ok] - o["h_gate"][ok])
     # (captured rays are left out: their last accepted step ends past the stop
     # radius, where H is ill-conditioned)
+    # a ray passes the full-maximum check within 1e-12 absolute or 1e-4
+    # relative (near the rounding level of H, ~1e-13, only the first is
+    # meaningful); h_drift_rel holds the relative difference beyond 1e-12
     esc = ok & (o["cls"] == 0)
-    errs["h_drift_rel"] = np.abs(g["h_drift"][esc] - o["h_drift"][esc]) / (np.abs(o["h_drift"][esc]) + 1e-12)
+    dh = np.abs(g["h_drift"][esc] - o["h_drift"][esc])
+    errs["h_drift_rel"] = np.where(dh <= 1e-12, 0.0, dh / (np.abs(o["h_drift"][esc]) + 1e-300))
     for k, v in errs.items():
         res[k] = {"max": float(v.max()) if v.size else 0.0,
                   "p50": float(np.median(v)) if v.size else 0.0,

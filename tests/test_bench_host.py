@@ -38,14 +38,30 @@ def test_attempts_histogram():
 def test_counters_only_for_matching_sources(tmp_path, monkeypatch):
     b = load_bench()
     good = {"source_sha256": b.kernel_source_hash(), "fetch_bytes": 1.0, "write_bytes": 2.0,
-            "launch": "256,1,1,4,2", "executed_fp64_flop": 5.0}
+            "launch": "256,2,1,8,3", "executed_fp64_flop": 5.0}
     f = tmp_path / "t.json"
     f.write_text(json.dumps(good))
-    monkeypatch.setattr(b, "TRAFFIC_FILE", str(f))
-    assert b.measured_traffic() == (3.0, "256,1,1,4,2")
-    assert b._committed_counters()["executed_fp64_flop"] == 5.0
+    monkeypatch.setattr(b, "COUNTER_FILE", str(f))
+    assert b.committed_counters()["executed_fp64_flop"] == 5.0
     f.write_text(json.dumps(dict(good, source_sha256="0" * 64)))
-    assert b.measured_traffic() == (None, None)
-    assert b._committed_counters() is None
-    monkeypatch.setattr(b, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
-    assert b.measured_traffic() == (None, None)
+    assert b.committed_counters() is None
+    monkeypatch.setattr(b, "COUNTER_FILE", str(tmp_path / "missing.json"))
+    assert b.committed_counters() is None
+
+
+def test_gate_stats_ignore_failed_rays():
+    b = load_bench()
+    o = {"cls": np.array([0, 1, 2, 0]), "h_gate": np.array([1e-9, 5e-9, 1.0, 2e-9])}
+    g = b.gate_stats(o)
+    assert g["holds"] and g["failed_rays"] == 1 and g["h_gate_max"] == 5e-9 and g["frac_le_1e-8"] == 1.0
+    o["h_gate"][3] = 2e-8
+    g = b.gate_stats(o)
+    assert not g["holds"] and g["frac_le_1e-8"] == 2 / 3
+
+
+def test_gate_tolerances_are_the_listed_ones():
+    b = load_bench()
+    assert b.GATE_RTOLS == (1e-8, 3e-9, 1e-9, 3e-10, 1e-10)
+    assert max(b.GATE_RTOLS_BEYOND) < min(b.GATE_RTOLS)
+    s = b.solver_at({"solver": {"rtol": 1e-8, "atol": 1e-10, "r_escape": 1100.0}}, 3e-10)
+    assert s["rtol"] == 3e-10 and s["atol"] == 3e-12

@@ -159,6 +159,31 @@ def test_more_cameras_than_the_lds_directory(T, orc):
         assert np.array_equal(gs["cls"], o["cls"]) and np.array_equal(gs["n_hits"], o["n_hits"])
 
 
+def test_schwarzschild_disk_table1_scene(T, orc):
+    """The scene of the paper's Table 1 (Sec. 4.3): Schwarzschild (a = 0) with the
+    Novikov-Thorne disk, D = 100, 80 deg.  At a = 0 the root x_2 of Eq. (12)
+    vanishes and its term of Eq. (11) is dropped; the redshift of Eq. (15) has
+    no frame dragging.  Full 64^2 and ragged 45 x 37 images at the FP64 bar."""
+    w = W.WORKLOADS["schwarzschild_disk_100"]
+    for nx, ny in ((64, 64), (45, 37)):
+        cam = dict(w["cameras"][0], nx=nx, ny=ny)
+        say("case schwarzschild_disk_100", nx, ny, "fp64")
+        g, o = full_image_parity(T, orc, w["a"], cam, w["disk"], w["solver"])
+        assert (o["n_hits"] > 0).sum() > 0.1 * nx * ny
+        assert (o["n_hits"] > 1).sum() > 0
+        # the shading uses the a = 0 Page-Thorne form on every hit
+        m = o["n_hits"] > 0
+        assert np.all(g["hit_flux"][m, 0] > 0)
+
+
+def test_schwarzschild_disk_table1_scene_mixed(T, orc):
+    w = W.WORKLOADS["schwarzschild_disk_100"]
+    cam = dict(w["cameras"][0], nx=64, ny=64)
+    say("case schwarzschild_disk_100 64x64 mixed")
+    g, o = full_image_parity(T, orc, w["a"], cam, w["disk"], w["solver"], precision=1, tol=MIXED_TOL, htol=None)
+    assert g["n_fp32"].sum() > 0
+
+
 @pytest.mark.parametrize("method", [1, 2], ids=["ck45", "rkf45"])
 def test_six_stage_pairs_full_images(T, orc, method):
     """Cash-Karp and Fehlberg (Sec. 3.2) on the Schwarzschild shadow and a ragged
@@ -178,32 +203,14 @@ def test_six_stage_pairs_full_images(T, orc, method):
 
 
 # ------------------------------------------------- Gragg-Bulirsch-Stoer
-# The extrapolation's error estimate T[K][K] - T[K][K-1] is a difference of two
-# states of size |y|; far from the hole the truncation error is below the
-# rounding of that difference, so the controller's step factor carries
-# rounding noise and the step sequence of two correct FP64 implementations
-# diverges (shown on the CPU: the oracle and its FMA-contracted build disagree
-# on the step count of ~half the rays).  Outputs then differ by the method's
-# own accuracy (events are read off the cubic interpolant of macro-steps
-# hundreds of M long).  Hence two bars: one macro-step, fixed by the arithmetic
-# alone, to 1e-12; whole images within a small multiple of the oracle's own
-# rounding spread.
+# The extrapolation's controller reading (Sec. 3.2 leaves it open): increments
+# extrapolated, error components below their rounding floor taken as zero, the
+# step factor rounded down to a power of two, so the step sequence does not
+# depend on the rounding of the estimate; events are located on the method's
+# own solution over the partial macro-step.  Parity is therefore held at the
+# FP64 bar, with the step counts compared too.
 GBS_NEAR_CAM = dict(r_obs=8.0, theta_obs=math.pi / 3, nx=24, ny=24, alpha_min=-5.0, alpha_max=5.0,
                     beta_min=-5.0, beta_max=5.0)
-SPREAD_FACTOR = 5.0
-
-
-def assert_within_spread(g, o, f, band, label):
-    rg, rf = compare(g, o, band, 0.0), compare(f, o, band, 0.0)
-    say(label, "gpu-oracle", {k: (rg[k]["p50"], rg[k]["max"]) for k in ("hit_r", "hit_g", "final_theta", "final_phi")})
-    say(label, "fma-oracle", {k: (rf[k]["p50"], rf[k]["max"]) for k in ("hit_r", "hit_g", "final_theta", "final_phi")})
-    assert rg["class_mismatch_off_band"] <= rf["class_mismatch_off_band"] + 2, (rg, rf)
-    for k in ("hit_r", "hit_g", "final_theta", "final_phi", "flux"):
-        assert rg[k]["p50"] <= SPREAD_FACTOR * rf[k]["p50"] + 1e-12, (k, rg[k], rf[k])
-        assert rg[k]["max"] <= 2 * SPREAD_FACTOR * rf[k]["max"] + 1e-9, (k, rg[k], rf[k])
-    same_go = np.mean(g["n_accept"] == o["n_accept"])
-    same_fo = np.mean(f["n_accept"] == o["n_accept"])
-    assert same_go >= 0.5 * same_fo, (same_go, same_fo)
 
 
 @pytest.mark.parametrize("h0_frac", [0.02, 0.1, 0.3, 1.0])
@@ -226,48 +233,34 @@ def test_extrapolation_first_macro_step(T, orc, h0_frac):
         assert np.allclose(g["h_drift"], o["h_drift"], rtol=1e-6, atol=1e-14)
 
 
-def test_extrapolation_full_images_within_rounding_spread(T, orc):
-    """Gragg-Bulirsch-Stoer (Sec. 3.2) on the Schwarzschild shadow and a ragged
-    Kerr image with the disk: the GPU's distance to the oracle is bounded by
-    the oracle's distance to its own FMA-contracted build."""
-    for name, nx, ny in (("schwarzschild_64", None, None), ("kerr09_512", 37, 29)):
-        w = W.WORKLOADS[name]
-        cam = dict(w["cameras"][0]) if nx is None else dict(w["cameras"][0], nx=nx, ny=ny)
-        sv = dict(w["solver"], method=3)
-        say("case gbs", name, cam["nx"], cam["ny"])
-        g = gpu_trace(T, w["a"], cam, w["disk"], sv)
-        o = oracle_trace(orc, w["a"], cam, w["disk"], sv)
-        m = orc.make_metric(w["a"])
-        f = orc.trace(m, [orc.make_camera(cam)], orc.make_disk(w["disk"]), orc.make_solver(sv), fma=True)
-        band = edge_band(class_key(o).reshape(cam["ny"], cam["nx"])).ravel()
-        assert_within_spread(g, o, f, band, name)
-        # macro-steps: far fewer attempts per ray than the 5(4) pair needs
-        d = gpu_trace(T, w["a"], cam, w["disk"], w["solver"])
-        assert (g["n_accept"] + g["n_reject"]).mean() < 0.5 * (d["n_accept"] + d["n_reject"]).mean()
+@pytest.mark.parametrize("name,nx,ny,rtol", [("schwarzschild_64", 64, 64, 1e-8), ("kerr09_512", 37, 29, 1e-8),
+                                             ("kerr09_512", 37, 29, 3e-10), ("schwarzschild_disk_100", 45, 37, 1e-8)])
+def test_extrapolation_full_images(T, orc, name, nx, ny, rtol):
+    """Gragg-Bulirsch-Stoer (Sec. 3.2) on the Schwarzschild shadow, a ragged
+    Kerr image with the disk (config and gate tolerances) and the Table 1
+    scene: the FP64 bar, and the same macro-steps as the oracle on every ray
+    off the edge band."""
+    w = W.WORKLOADS[name]
+    cam = dict(w["cameras"][0], nx=nx, ny=ny)
+    sv = dict(w["solver"], rtol=rtol, atol=rtol / 100, method=3)
+    say("case gbs", name, nx, ny, rtol)
+    g, o = full_image_parity(T, orc, w["a"], cam, w["disk"], sv)
+    band = edge_band(class_key(o).reshape(ny, nx)).ravel()
+    same = (g["n_accept"] == o["n_accept"]) & (g["n_reject"] == o["n_reject"])
+    say("step counts identical on", same.mean(), "off band", same[~band].mean())
+    assert same[~band].mean() >= 0.999
+    # macro-steps: far fewer attempts per ray than the 5(4) pair needs
+    d = gpu_trace(T, w["a"], cam, w["disk"], dict(sv, method=0))
+    assert (g["n_accept"] + g["n_reject"]).mean() < 0.5 * (d["n_accept"] + d["n_reject"]).mean()
 
 
 def test_extrapolation_kerr09_512_sampled(T, orc):
-    """The 512^2 Kerr image with the disk at the gate tolerance, sampled."""
+    """The 512^2 Kerr image with the disk at the gate tolerance, 200 sampled
+    pixels and their neighbours, at the FP64 bar."""
     w = W.WORKLOADS["kerr09_512"]
-    cam = w["cameras"][0]
     sv = dict(w["solver"], rtol=3e-10, atol=3e-12, method=3)
     say("case kerr09_512 gbs sampled")
-    g = gpu_trace(T, w["a"], cam, w["disk"], sv)
-    nx, ny, nsample = cam["nx"], cam["ny"], 200
-    rng = np.random.default_rng(5)
-    ii, jj = rng.integers(1, nx - 1, nsample), rng.integers(1, ny - 1, nsample)
-    ids = np.array([(j + dj) * nx + (i + di) for i, j in zip(ii, jj) for dj in (-1, 0, 1) for di in (-1, 0, 1)])
-    uniq, inv = np.unique(ids, return_inverse=True)
-    m = orc.make_metric(w["a"])
-    args = (m, [orc.make_camera(cam)], orc.make_disk(w["disk"]), orc.make_solver(sv))
-    o_u, f_u = orc.trace(*args, ray_ids=uniq), orc.trace(*args, ray_ids=uniq, fma=True)
-    key9 = class_key(o_u)[inv].reshape(nsample, 9)
-    band = np.any(key9 != key9[:, 4:5], axis=1)
-    centre = inv.reshape(nsample, 9)[:, 4]
-    o = {k: v[centre] for k, v in o_u.items()}
-    f = {k: v[centre] for k, v in f_u.items()}
-    gs = {k: v[uniq[centre]] for k, v in g.items()}
-    assert_within_spread(gs, o, f, band, "kerr09_512 sampled")
+    g, res = sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], sv, 0, 200, 5, FP64_TOL, FP64_HTOL)
     assert np.all(g["cls"] != 2)
 
 
@@ -550,27 +543,37 @@ def test_tabulated_vs_analytic_on_gpu(T, orc):
 
 
 def test_tabulated_64_cameras_sampled(T, orc):
-    """All 64 cameras (512^2 each) in one launch; sampled pixels against the oracle."""
-    import torch
+    """All 64 cameras (512^2 each) in one launch; 400 sampled pixels and their 8
+    neighbours traced by the oracle.  Classes must be identical off the edge
+    band (a sample with a neighbour of another oracle class); every class
+    difference must lie in that band; values on matching off-band samples
+    within the tabulated bar."""
     w, a, nr, nth, r_min, r_max = c5_setup(orc)
     tab_g = gpu_table(T, a, nr, nth, r_min, r_max)
     tab_o = orc.build_kerr_table(a, nr, nth, r_min, r_max)
     cams = w["cameras"]
     say("case tabulated 64 cameras x 512^2 fp64")
     g = gpu_trace(T, a, cams, w["disk"], w["solver"], table=(tab_g, nr, nth, r_min, r_max))
-    per = 512 * 512
+    nx = ny = 512
+    per = nx * ny
+    nsample = 400
     rng = np.random.default_rng(5)
-    ids = np.sort(rng.choice(64 * per, 96, replace=False)).astype(np.int64)
-    o = orc.trace(orc.make_metric(a, tab_o, nr, nth, r_min, r_max), [orc.make_camera(c) for c in cams],
-                  orc.make_disk(w["disk"]), orc.make_solver(w["solver"]), ray_ids=ids)
-    gs = {k: v[ids] for k, v in g.items()}
-    band = np.zeros(len(ids), dtype=bool)
+    cc = rng.integers(0, len(cams), nsample)
+    ii, jj = rng.integers(1, nx - 1, nsample), rng.integers(1, ny - 1, nsample)
+    ids = np.array([c * per + (j + dj) * nx + (i + di) for c, i, j in zip(cc, ii, jj)
+                    for dj in (-1, 0, 1) for di in (-1, 0, 1)], dtype=np.int64)
+    uniq, inv = np.unique(ids, return_inverse=True)
+    o_u = orc.trace(orc.make_metric(a, tab_o, nr, nth, r_min, r_max), [orc.make_camera(c) for c in cams],
+                    orc.make_disk(w["disk"]), orc.make_solver(w["solver"]), ray_ids=uniq)
+    key9 = class_key(o_u)[inv].reshape(nsample, 9)
+    band = np.any(key9 != key9[:, 4:5], axis=1)
+    centre = inv.reshape(nsample, 9)[:, 4]
+    o = {k: v[centre] for k, v in o_u.items()}
+    gs = {k: v[uniq[centre]] for k, v in g.items()}
     res = compare(gs, o, band, TAB_TOL)
     say(res)
-    # sampled pixels: a class differing from the oracle must sit on a class boundary
-    mism = np.flatnonzero(class_key(gs) != class_key(o))
-    assert len(mism) <= 2, mism
-    keep = class_key(gs) == class_key(o)
-    res = compare({k: v[keep] for k, v in gs.items()}, {k: v[keep] for k, v in o.items()}, band[keep], TAB_TOL)
+    mism = class_key(gs) != class_key(o)
+    say("band", int(band.sum()), "class differences", int(mism.sum()), "of which in the band", int((mism & band).sum()))
+    assert not np.any(mism & ~band), np.flatnonzero(mism & ~band)
     assert_parity(res, TAB_TOL, TAB_HTOL)
     assert np.all(g["cls"] != 2)

@@ -18,6 +18,11 @@ Image workloads (observer distance D = r_obs in units of M, angles in radians):
   over [-25, 25]^2; disk r_ISCO .. 20.
 * ``osiris_1024``        a = 0.98, theta_obs = 90 deg, 1024 x 1024 over [-8, 8]^2
   (the paper's calibration scene, Sec. 4.3), no disk.
+* ``schwarzschild_disk_100`` the scene of the paper's Table 1 (Sec. 4.3):
+  Schwarzschild (a = 0) with a Novikov-Thorne disk seen from D = r_obs = 100;
+  the paper leaves the inclination, window, disk size and tolerance unstated:
+  theta_obs = 80 deg, 512 x 512 over [-22, 22]^2, disk r_ISCO (6 M) .. 20 M,
+  escape at 1.1 r_obs = 110 M, rtol = 1e-8.
 
 The solver defaults: rtol = 1e-8, atol = 1e-10, first step 0.01 r_obs, escape at
 1.1 r_obs (1100 M), horizon stop at 1.01 r_+, event tolerance 1e-12 in lambda.
@@ -60,6 +65,9 @@ WORKLOADS = {
         table=dict(nr=512, nth=256, r_min_over_rplus=1.1, r_max=2000.0)),
     "osiris_1024": dict(
         a=0.98, cameras=[camera(1000.0, 90.0, 1024, 1024, 8.0)], disk=None, solver=solver()),
+    "schwarzschild_disk_100": dict(
+        a=0.0, cameras=[camera(100.0, 80.0, 512, 512, 22.0)],
+        disk=dict(r_in=0.0, r_out=20.0, max_hits=3), solver=solver(r_escape=110.0)),
 }
 
 
