@@ -244,6 +244,20 @@ def gate_search(T, S, prec):
     return table, first
 
 
+def tabulated_scene(T, torch, W):
+    """The 64-camera batch on the tabulated a = 0.7 metric (table built on the
+    device from analytic Kerr) and the launch shape measured best for it."""
+    w = W.WORKLOADS["tabulated07_64cams"]
+    t = w["table"]
+    r_min = t["r_min_over_rplus"] * (1.0 + np.sqrt(1.0 - w["a"] ** 2))
+    tab = torch.zeros(5 * t["nr"] * t["nth"] * 4, dtype=torch.float64, device="cuda")
+    T.tartarus_build_kerr_table(w["a"], t["nr"], t["nth"], r_min, t["r_max"], tab)
+    S = Scene(T, W, "tabulated07_64cams")
+    S.metric = T.make_metric(w["a"], tab, t["nr"], t["nth"], r_min, t["r_max"])
+    S.table = tab                # keeps the table alive with the scene
+    return S, T.make_launch(256, 2, 1, 4, T.ORDER_PIXEL)
+
+
 def workload_legs(T, torch, W, steps, autotune: bool) -> dict:
     """Other image workloads at their config tolerance (rtol 1e-8): the
     Schwarzschild shadow, the paper's OSIRIS calibration scene, the paper's
@@ -261,14 +275,7 @@ def workload_legs(T, torch, W, steps, autotune: bool) -> dict:
         key = name if nx is None else f"{name}_{nx}"
         legs[key] = leg_record(T, torch, S, la, steps, 1, launch)
         del S
-    w = W.WORKLOADS["tabulated07_64cams"]
-    t = w["table"]
-    r_min = t["r_min_over_rplus"] * (1.0 + np.sqrt(1.0 - w["a"] ** 2))
-    tab = torch.zeros(5 * t["nr"] * t["nth"] * 4, dtype=torch.float64, device="cuda")
-    T.tartarus_build_kerr_table(w["a"], t["nr"], t["nth"], r_min, t["r_max"], tab)
-    S = Scene(T, W, "tabulated07_64cams")
-    S.metric = T.make_metric(w["a"], tab, t["nr"], t["nth"], r_min, t["r_max"])
-    launch = T.make_launch(256, 2, 1, 4, T.ORDER_PIXEL)
+    S, launch = tabulated_scene(T, torch, W)
     log("bench: workload tabulated07_64cams")
     legs["tabulated07_64cams"] = leg_record(T, torch, S, S.args(), 2, 1, launch)
     return legs
@@ -398,6 +405,8 @@ def main():
                     help="with --only-headline: the precision of the traced headline")
     ap.add_argument("--only-headline", action="store_true",
                     help="trace the headline image only (for profilers): no search, no legs")
+    ap.add_argument("--only-tabulated", action="store_true",
+                    help="trace the 64-camera tabulated batch only (for profilers)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-latency leg")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -425,6 +434,11 @@ def main():
         return
 
     T.tartarus_init(0, 0)
+    if args.only_tabulated:
+        S, launch = tabulated_scene(T, torch, W)
+        rec = leg_record(T, torch, S, S.args(), args.steps, args.warmup, launch)
+        print(json.dumps({"only_tabulated": rec}))
+        return
     S = Scene(T, W, HEADLINE)
     forced = T.make_launch(*[int(v) for v in args.launch.split(",")]) if args.launch else None
 

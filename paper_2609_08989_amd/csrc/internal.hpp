@@ -118,6 +118,7 @@ struct LaunchArgs {
     int pad3;
 };
 
-constexpr int SLOT_DOUBLES = 32;
+constexpr int SLOT_DOUBLES = 40;   // a parked ray (31 doubles) and its event search (8)
+
 
 }  // namespace tartarus

@@ -46,6 +46,7 @@ extern "C" hipError_t tartarus_launch_fill_u32(unsigned int* p, unsigned int v, 
 extern "C" hipError_t tartarus_launch_fill_u64(unsigned long long* p, unsigned long long v, long long n,
                                                hipStream_t stream);
 
+
 namespace {
 
 int hip_fail(hipError_t e, const char* what)
@@ -174,79 +175,56 @@ int resolve_launch(int kind, int prec, int method, const tartarus_launch* req, t
     return finish_shape(L, occ, n_rays, g_dev.cus, grid);
 }
 
-// Enqueue one trace (no validation) on the stream.
-int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, int ncams, const tartarus_disk* disk,
-                  const tartarus_solver* solver, const tartarus_outputs* out, const tartarus_launch* launch,
-                  hipStream_t stream)
+// Device memory one trace works in.
+struct TraceMem {
+    DevJob* djobs;                  // job table, already filled on the stream
+    JobConst* djc;                  // per-job constants (written by job_setup)
+    unsigned long long* head;       // queue head
+    unsigned int* order;            // cost-ordered queue: order[n], then
+    unsigned char* key;             //   key[n],
+    unsigned int* count;            //   count[kOrderBuckets], cursor[kOrderBuckets]
+    double* inter;                  // tabulated metric interleaved by grid point
+};
+
+bool cost_ordered(const tartarus_launch& L, long long n)
 {
-    const int kind = metric->kind, prec = solver->precision, method = solver->method;
-    tartarus_launch L;
-    int grid = 0;
-    const long long n_rays = (long long)cams[0].nx * cams[0].ny * ncams;
-    int rc = resolve_launch(kind, prec, method, launch, L, grid, n_rays);
-    if (rc) return rc;
-    Slot* S = nullptr;
-    if ((rc = take_slot(ncams, S))) return rc;
-    const long long per = (long long)cams[0].nx * cams[0].ny;
-    const size_t nrec = (size_t)per * ncams;
-    if (nrec > S->rec_cap) {
-        if (S->rec) (void)hipFree(S->rec);
-        S->rec = nullptr;
-        S->rec_cap = 0;
-        HIP_TRY(hipMalloc(&S->rec, nrec * REC_DOUBLES * sizeof(double)));
-        S->rec_cap = nrec;
-    }
-    for (int c = 0; c < ncams; ++c)
-        fill_job(S->hjobs[c], metric, cams[c], disk, solver, out, c * per, c * per, S->rec + (size_t)c * per * REC_DOUBLES);
-    HIP_TRY(hipMemcpyAsync(S->djobs, S->hjobs, sizeof(DevJob) * ncams, hipMemcpyHostToDevice, stream));
-    HIP_TRY(tartarus_launch_fill_u64(S->head, 0ull, 1, stream));
+    return n <= 0xffffffffll &&
+           (L.order == TARTARUS_ORDER_COST || (L.order == TARTARUS_ORDER_DEFAULT && n >= kCostOrderMin));
+}
+
+// The device part of a trace, on the stream, after the job table: queue head,
+// set-up, (table interleave,) cost order, integrator (bracketed by an event
+// pair when timed), finishing pass.
+int launch_sequence(const tartarus_metric* metric, const tartarus_solver* solver, const tartarus_launch& L, int grid,
+                    int ncams, long long per, const TraceMem& M, bool timed, hipStream_t stream)
+{
+    const int kind = metric->kind, prec = kernel_precision(solver), method = solver->method;
+    HIP_TRY(tartarus_launch_fill_u64(M.head, 0ull, 1, stream));
     LaunchArgs A;
     fill_args(A, metric, solver);
-    A.jobs = S->djobs;
-    A.jc = S->djc;
+    A.jobs = M.djobs;
+    A.jc = M.djc;
     A.njobs = ncams;
     A.chunk = L.chunk;
     A.refill_min = L.refill_min;
     A.first_ray = 0;
     A.total_rays = per * ncams;
-    A.head = S->head;
+    A.head = M.head;
     HIP_TRY(tartarus_launch_setup(kind, &A, stream));
     if (kind == TARTARUS_METRIC_TABLE) {
-        const size_t need = (size_t)metric->nr * metric->nth * 20;
-        if (need > S->inter_cap) {
-            if (S->inter) (void)hipFree(S->inter);
-            S->inter = nullptr;
-            S->inter_cap = 0;
-            HIP_TRY(hipMalloc(&S->inter, need * sizeof(double)));
-            S->inter_cap = need;
-        }
-        HIP_TRY(tartarus_launch_table_interleave(&A, S->inter, stream));
-        A.table_inter = S->inter;
+        HIP_TRY(tartarus_launch_table_interleave(&A, M.inter, stream));
+        A.table_inter = M.inter;
     }
     const long long n = A.total_rays;
-    const bool cost = n <= 0xffffffffll &&
-                      (L.order == TARTARUS_ORDER_COST || (L.order == TARTARUS_ORDER_DEFAULT && n >= kCostOrderMin));
-    if (cost) {
-        const size_t key_bytes = ((size_t)n + 255) / 256 * 256;
-        const size_t need = (size_t)n * 4 + key_bytes + 2 * kOrderBuckets * sizeof(unsigned int);
-        if (need > S->ord_cap) {
-            if (S->ord) (void)hipFree(S->ord);
-            S->ord = nullptr;
-            S->ord_cap = 0;
-            HIP_TRY(hipMalloc(&S->ord, need));
-            S->ord_cap = need;
-        }
-        unsigned int* order = reinterpret_cast<unsigned int*>(S->ord);
-        unsigned char* key = S->ord + (size_t)n * 4;
-        unsigned int* count = reinterpret_cast<unsigned int*>(key + key_bytes);
-        unsigned int* cursor = count + kOrderBuckets;
-        HIP_TRY(tartarus_launch_fill_u32(count, 0u, kOrderBuckets, stream));
-        HIP_TRY(tartarus_launch_order(&A, n, key, count, cursor, order, stream));
-        A.order = order;
+    if (cost_ordered(L, n)) {
+        unsigned int* cursor = M.count + kOrderBuckets;
+        HIP_TRY(tartarus_launch_fill_u32(M.count, 0u, kOrderBuckets, stream));
+        HIP_TRY(tartarus_launch_order(&A, n, M.key, M.count, cursor, M.order, stream));
+        A.order = M.order;
     }
     A.tile = L.order == TARTARUS_ORDER_TILE ? 1 : 0;
-    std::pair<hipEvent_t, hipEvent_t> kt(nullptr, nullptr);
-    if (g_dev.ktime_on) {
+    if (timed) {
+        std::pair<hipEvent_t, hipEvent_t> kt(nullptr, nullptr);
         if (!g_dev.ktime_spare.empty()) {
             kt = g_dev.ktime_spare.back();
             g_dev.ktime_spare.pop_back();
@@ -272,6 +250,62 @@ int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, in
     }
     for (int c0 = 0; c0 < ncams; c0 += 65535)
         HIP_TRY(tartarus_launch_finish(&A, c0, std::min(65535, ncams - c0), per, stream));
+    return TARTARUS_OK;
+}
+
+// Enqueue one trace (no validation) on the stream, with the per-call slot's
+// growable buffers.
+int enqueue_trace(const tartarus_metric* metric, const tartarus_camera* cams, int ncams, const tartarus_disk* disk,
+                  const tartarus_solver* solver, const tartarus_outputs* out, const tartarus_launch* launch,
+                  hipStream_t stream)
+{
+    const int kind = metric->kind, prec = kernel_precision(solver), method = solver->method;
+    tartarus_launch L;
+    int grid = 0;
+    const long long n_rays = (long long)cams[0].nx * cams[0].ny * ncams;
+    int rc = resolve_launch(kind, prec, method, launch, L, grid, n_rays);
+    if (rc) return rc;
+    Slot* S = nullptr;
+    if ((rc = take_slot(ncams, S))) return rc;
+    const long long per = (long long)cams[0].nx * cams[0].ny;
+    const size_t nrec = (size_t)per * ncams;
+    if (nrec > S->rec_cap) {
+        if (S->rec) (void)hipFree(S->rec);
+        S->rec = nullptr;
+        S->rec_cap = 0;
+        HIP_TRY(hipMalloc(&S->rec, nrec * REC_DOUBLES * sizeof(double)));
+        S->rec_cap = nrec;
+    }
+    TraceMem M{S->djobs, S->djc, S->head, nullptr, nullptr, nullptr, nullptr};
+    if (kind == TARTARUS_METRIC_TABLE) {
+        const size_t need = (size_t)metric->nr * metric->nth * 20;
+        if (need > S->inter_cap) {
+            if (S->inter) (void)hipFree(S->inter);
+            S->inter = nullptr;
+            S->inter_cap = 0;
+            HIP_TRY(hipMalloc(&S->inter, need * sizeof(double)));
+            S->inter_cap = need;
+        }
+        M.inter = S->inter;
+    }
+    if (cost_ordered(L, n_rays)) {
+        const size_t key_bytes = ((size_t)n_rays + 255) / 256 * 256;
+        const size_t need = (size_t)n_rays * 4 + key_bytes + 2 * kOrderBuckets * sizeof(unsigned int);
+        if (need > S->ord_cap) {
+            if (S->ord) (void)hipFree(S->ord);
+            S->ord = nullptr;
+            S->ord_cap = 0;
+            HIP_TRY(hipMalloc(&S->ord, need));
+            S->ord_cap = need;
+        }
+        M.order = reinterpret_cast<unsigned int*>(S->ord);
+        M.key = S->ord + (size_t)n_rays * 4;
+        M.count = reinterpret_cast<unsigned int*>(M.key + key_bytes);
+    }
+    for (int c = 0; c < ncams; ++c)
+        fill_job(S->hjobs[c], metric, cams[c], disk, solver, out, c * per, c * per, S->rec + (size_t)c * per * REC_DOUBLES);
+    HIP_TRY(hipMemcpyAsync(S->djobs, S->hjobs, sizeof(DevJob) * ncams, hipMemcpyHostToDevice, stream));
+    if ((rc = launch_sequence(metric, solver, L, grid, ncams, per, M, g_dev.ktime_on, stream))) return rc;
     HIP_TRY(hipEventRecord(S->ev, stream));
     S->pending = true;
     return TARTARUS_OK;
@@ -397,7 +431,7 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
     if (!g_dev.ready) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
     HIP_TRY(hipSetDevice(g_dev.id));
     hipStream_t stream = (hipStream_t)hip_stream;
-    const int kind = metric->kind, prec = solver->precision, method = solver->method;
+    const int kind = metric->kind, prec = kernel_precision(solver), method = solver->method;
     g_dev.tuned.erase(tune_key(kind, prec, method));
     tartarus_launch cur = default_launch(kind, prec, method);
     int grid = 0;
@@ -861,7 +895,7 @@ int server_round(std::unique_lock<std::mutex>& lk)
     A.ndir = nd;
     A.remaining = S.dremaining;
     if (!fresh.empty()) HIP_TRY(tartarus_launch_setup(TARTARUS_METRIC_KERR, &A, S.stream));
-    HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, sv.precision, sv.method, &A, S.grid, S.block, S.stream));
+    HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, kernel_precision(&sv), sv.method, &A, S.grid, S.block, S.stream));
     HIP_TRY(hipMemcpyAsync(S.hremaining, S.dremaining, sizeof(unsigned int) * kMaxEntries, hipMemcpyDeviceToHost,
                            S.stream));
     HIP_TRY(hipMemcpyAsync(S.hhead, S.dhead, sizeof(unsigned long long), hipMemcpyDeviceToHost, S.stream));
@@ -891,7 +925,7 @@ void server_main()
     Server& S = g_srv;
     std::unique_lock<std::mutex> lk(S.mu);
     if (!S.dev_ready) {
-        int rc = server_alloc(S.solver.precision, S.solver.method);
+        int rc = server_alloc(kernel_precision(&S.solver), S.solver.method);
         if (rc) {
             S.dev_error = tartarus_last_error();
             S.running = false;

@@ -947,19 +947,6 @@ __device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>
     M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
 }
 
-// The extrapolation's own solution at lambda + sh: one macro-step of length sh
-// from the ray's state (no error control), and the slope there.  Event roots
-// of the extrapolation are located on it: a macro-step spans up to hundreds of
-// M, over which the cubic Hermite interpolant is accurate to ~1e-3 only.
-template <int KIND>
-__device__ __forceinline__ void gbs_point(const Ray& R, const MetricOps<KIND>& M, double sh, Deriv<double>& y,
-                                       Deriv<double>& k)
-{
-    Deriv<double> e;
-    double H, c;
-    stages64_gbs<KIND>(R, M, sh, 0.0, 0.0, y, k, e, H, c);
-}
-
 // Verlet (Sec. 3.2): a fixed step of the generalized Stormer-Verlet scheme for
 // the non-separable H(x, p) = 1/2 g^{ab}(x) p_a p_b, symmetric and symplectic:
 //   p' = p - (h/2) dH/dx(x, p')                      (implicit in p')
@@ -1112,86 +1099,134 @@ __device__ __forceinline__ double step_factor(double err2, double fmx)
     return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<2 * P>(err2)));
 }
 
-// Root in (0, 1] of an event on the extrapolation's own solution over the
-// accepted macro-step [lam, lam + h]: of cos(theta) (disk) or of r - target
-// (radial).  Newton's method on g(s) = event(Phi(s h)), with the slope from
-// f at Phi(s h), starting from the root s0 of the step's cubic; the bracket
-// [lo, hi] keeps the start side at lo, and a Newton step leaving it bisects.
-// Stops when the Newton correction or the bracket is at most tol in lambda;
-// returns the last evaluated point, within tol of the root, with its state in
-// y.  At most 64 iterations.
-template <int KIND>
-__device__ double gbs_root(const Ray& R, const MetricOps<KIND>& M, double h, bool disk, double target, double s0,
-                           double tol, Deriv<double>& y)
+// Event search of the extrapolation.  A macro-step spans up to hundreds of M,
+// over which the step's cubic Hermite interpolant is accurate to ~1e-3 only,
+// so an event root is located on the method's own solution: a probe at s is
+// one macro-step of length s h from the step's start (the same sweeps and
+// columns, without error control).  The search runs across iterations of the
+// persistent loop: after an accepted macro-step with an event the ray stays at
+// the step's start, and each of its following iterations is one probe through
+// the same stages64_gbs call as an attempt, so a wavefront runs that code once
+// per iteration whatever its lanes are doing (a probe inside the attempt's
+// iteration would run with one lane active while the others wait).  Newton's
+// method from the cubic's root, safeguarded by the bracket [lo, hi] (the start
+// side at lo): the terminal root first, then an equatorial crossing in the
+// same step (it counts when it is not after the terminal root); after a
+// crossing that does not end the ray, a last probe at s = 1 rebuilds the
+// step's end, bit for bit as the attempt produced it, and the ray advances.
+struct GbsSearch {
+    double h;          // the accepted macro-step being searched
+    double lo, hi, s;  // bracket and current probe, in units of h
+    double target;     // radial target of the terminal event
+    double fac;        // the controller's factor for the step after it
+    double s_disk;     // the cubic's equatorial root: where the disk search starts
+    int phase;         // 0 attempts; 1 terminal root; 2 equatorial root; 3 rebuild the step's end
+    int flags;         // 1 horizon, 2 escape, 4 equator crossed; probes of this search above bit 8
+};
+constexpr int kGbsMaxProbes = 64;
+
+__device__ __forceinline__ void gbs_search_start(GbsSearch& S, double s0)
 {
-    const bool above = disk ? R.cth > 0.0 : R.r - target > 0.0;
-    double lo = 0.0, hi = 1.0;
-    double s = (s0 > 0.0 && s0 <= 1.0) ? s0 : 0.5;
-    for (int it = 0; it < 64; ++it) {
-        Deriv<double> k;
-        gbs_point<KIND>(R, M, s * h, y, k);
-        double g, dg;
-        if (disk) {
-            double sn, cs;
-            sincos64(y.th, &sn, &cs);
-            g = cs;
-            dg = -sn * k.th * h;
-        } else {
-            g = y.r - target;
-            dg = k.r * h;
-        }
-        if (above ? g > 0.0 : g < 0.0)
-            lo = s;
-        else
-            hi = s;
-        double sn = s - g / dg;
-        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);   // also a zero or non-finite slope
-        if (fabs(sn - s) * h <= tol || (hi - lo) * h <= tol) break;
-        s = sn;
-    }
-    return s;
+    S.lo = 0.0;
+    S.hi = 1.0;
+    S.s = (s0 > 0.0 && s0 <= 1.0) ? s0 : 0.5;
+    S.flags &= 0xff;
 }
 
-// Events of an accepted macro-step of the extrapolation, located on its own
-// solution and taken in root order (a disk crossing at or before the terminal
-// root counts, one after it does not); the located hits and the terminal point
-// go to the record as final values.  Returns true when the ray has ended.
-template <int KIND>
-__device__ bool gbs_events(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M, double h,
-                           const Deriv<double>& y5, const Deriv<double>& k7, bool hz, bool es, bool dk,
-                           double target)
+// The ray moves to the end of its accepted step.
+__device__ __forceinline__ void advance(Ray& R, double h, double fac, const Deriv<double>& y5, const Deriv<double>& k7,
+                                        double c5, bool used32)
 {
+    R.lam += h;
+    R.t = y5.t;
+    R.r = y5.r;
+    R.th = y5.th;
+    R.ph = y5.ph;
+    R.pr = y5.pr;
+    R.pth = y5.pth;
+    R.k = k7;
+    R.k32 = used32 ? 1 : 0;
+    R.cth = c5;
+    R.h = h * fac;
+    R.rej_prev = 0;
+}
+
+// One probe of an event search, with the solution y at s and its slope k.
+// Returns true when the ray has ended.
+__device__ bool gbs_probe(Ray& R, GbsSearch& S, const LaunchArgs& A, const Deriv<double>& y, const Deriv<double>& k,
+                          double c)
+{
+    if (S.phase == 3) {
+        advance(R, S.h, S.fac, y, k, c, false);
+        S.phase = 0;
+        return false;
+    }
+    const bool disk = S.phase == 2;
+    double g, dg;
+    if (disk) {
+        double sn, cs;
+        sincos64(y.th, &sn, &cs);
+        g = cs;
+        dg = -sn * k.th * S.h;
+    } else {
+        g = y.r - S.target;
+        dg = k.r * S.h;
+    }
+    const bool above = disk ? R.cth > 0.0 : R.r - S.target > 0.0;
+    if (above ? g > 0.0 : g < 0.0)
+        S.lo = S.s;
+    else
+        S.hi = S.s;
+    double sn = S.s - g / dg;
+    if (!(sn > S.lo && sn < S.hi)) sn = 0.5 * (S.lo + S.hi);   // also a zero or non-finite slope
     const double tol = 0.125 * A.event_tol;
-    const Cubic pr(R.r, R.k.r, y5.r, k7.r, h);
-    const Cubic pth(R.th, R.k.th, y5.th, k7.th, h);
-    const bool term = hz | es;
-    Deriv<double> yt, yd;
-    double st = 2.0, sd = 2.0;
-    if (term) st = gbs_root<KIND>(R, M, h, false, target, locate_root(pr, target, hz, h, 1e-6 * h), tol, yt);
-    if (dk) sd = gbs_root<KIND>(R, M, h, true, 0.0, equator_root(pth, R.th, y5.th, R.cth, h, 1e-6 * h), tol, yd);
-    int cls = hz ? CLS_CAPTURED : CLS_ESCAPED;
-    if (dk && sd <= st) {
+    S.flags += 256;
+    if (!(fabs(sn - S.s) * S.h <= tol || (S.hi - S.lo) * S.h <= tol || (S.flags >> 8) >= kGbsMaxProbes)) {
+        S.s = sn;
+        return false;
+    }
+    // the root is S.s, within tol in lambda; y is the solution there
+    const int cls = (S.flags & 1) ? CLS_CAPTURED : CLS_ESCAPED;
+    double* term = R.rec + REC_TERM;
+    if (!disk) {
+        term[0] = y.r;
+        term[4] = y.th;
+        term[8] = y.ph;
+        term[13] = S.s;
+        if (S.flags & 4) {
+            S.phase = 2;
+            gbs_search_start(S, S.s_disk);
+            return false;
+        }
+        ray_finish(R, A, cls, 0);
+        return true;
+    }
+    const bool terminal = (S.flags & 3) != 0;
+    if (!terminal || S.s <= term[13]) {
         R.n_cross++;
-        const double rr = yd.r;
-        if (rr >= R.r_in && rr <= R.r_out && R.n_hits < R.max_hits) {
+        if (y.r >= R.r_in && y.r <= R.r_out && R.n_hits < R.max_hits) {
             double* sl = R.rec + REC_SLOT_LEN * R.n_hits;
-            sl[0] = rr;
+            sl[0] = y.r;
             sl[8] = 0.0;
-            sl[9] = fma(sd, h, R.lam);
+            sl[9] = fma(S.s, S.h, R.lam);
             reinterpret_cast<int*>(R.rec + REC_INTS)[6 + R.n_hits] = R.n_cross;
             R.n_hits++;
             if (R.opaque) {
-                yt = yd;
-                cls = CLS_ON_DISK;
+                term[0] = y.r;
+                term[4] = y.th;
+                term[8] = y.ph;
+                ray_finish(R, A, CLS_ON_DISK, 0);
+                return true;
             }
         }
     }
-    if (!term && cls != CLS_ON_DISK) return false;
-    R.rec[REC_TERM + 0] = yt.r;
-    R.rec[REC_TERM + 4] = yt.th;
-    R.rec[REC_TERM + 8] = yt.ph;
-    ray_finish(R, A, cls, 0);
-    return true;
+    if (terminal) {
+        ray_finish(R, A, cls, 0);
+        return true;
+    }
+    S.phase = 3;
+    S.s = 1.0;
+    return false;
 }
 
 // The largest power of two not above x (x > 0, finite): the extrapolation's
@@ -1203,14 +1238,17 @@ __device__ __forceinline__ double pow2_floor(double x)
 }
 
 // One attempt; returns true when the ray has terminated (outputs written).
+// (S: the extrapolation's event search; unused by the other methods.)
 template <int KIND, int PREC, int METHOD>
-__device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
+__device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const MetricOps<KIND>& M)
 {
-    if ((long long)R.n_acc + R.n_rej >= A.max_steps) {
+    bool probe = false;
+    if constexpr (METHOD == METHOD_GBS) probe = S.phase != 0;
+    if (!probe && (long long)R.n_acc + R.n_rej >= A.max_steps) {
         ray_fail(R, A);
         return true;
     }
-    const double h = R.h;
+    const double h = probe ? S.s * S.h : R.h;
     Deriv<double> y5, k7, e;
     double H5, c5;
     bool used32 = false;
@@ -1235,9 +1273,13 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
             if constexpr (METHOD == METHOD_DP45)
                 stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
             else if constexpr (METHOD == METHOD_GBS)
-                stages64_gbs<KIND>(R, M, h, A.atol, A.rtol, y5, k7, e, H5, c5);
+                // one call site for attempts and probes (a probe has no error control)
+                stages64_gbs<KIND>(R, M, h, probe ? 0.0 : A.atol, probe ? 0.0 : A.rtol, y5, k7, e, H5, c5);
             else
                 stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
+        }
+        if constexpr (METHOD == METHOD_GBS) {
+            if (probe) return gbs_probe(R, S, A, y5, k7, c5);
         }
         R.n_f32 += used32 ? 1 : 0;
         const double atol = A.atol, rtol = A.rtol;
@@ -1299,7 +1341,23 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
     const bool es = (R.r - r_esc < 0.0) && (y5.r - r_esc >= 0.0);
     const bool dk = R.max_hits > 0 && ((R.cth > 0.0 && c5 <= 0.0) || (R.cth < 0.0 && c5 >= 0.0));
     if constexpr (METHOD == METHOD_GBS) {
-        if ((hz | es | dk) && gbs_events<KIND>(R, A, M, h, y5, k7, hz, es, dk, hz ? r_stop : r_esc)) return true;
+        if (hz | es | dk) {
+            // the ray stays at the step's start while its events are searched
+            S.h = h;
+            S.fac = fac;
+            S.flags = (hz ? 1 : 0) | (es ? 2 : 0) | (dk ? 4 : 0);
+            S.s_disk = 0.5;
+            if (dk) S.s_disk = equator_root(Cubic(R.th, R.k.th, y5.th, k7.th, h), R.th, y5.th, R.cth, h, 1e-6 * h);
+            if (hz | es) {
+                S.phase = 1;
+                S.target = hz ? r_stop : r_esc;
+                gbs_search_start(S, locate_root(Cubic(R.r, R.k.r, y5.r, k7.r, h), S.target, hz, h, 1e-6 * h));
+            } else {
+                S.phase = 2;
+                gbs_search_start(S, S.s_disk);
+            }
+            return false;
+        }
     } else if (hz | es) {
         // terminal step: the finishing pass locates the root (and a crossing
         // of the equator before it) on the step's cubics; at most one radial
@@ -1320,18 +1378,7 @@ __device__ bool ray_step(Ray& R, const LaunchArgs& A, const MetricOps<KIND>& M)
         }
     }
 
-    R.lam += h;
-    R.t = y5.t;
-    R.r = y5.r;
-    R.th = y5.th;
-    R.ph = y5.ph;
-    R.pr = y5.pr;
-    R.pth = y5.pth;
-    R.k = k7;
-    R.k32 = used32 ? 1 : 0;
-    R.cth = c5;
-    R.h = h * fac;
-    R.rej_prev = 0;
+    advance(R, h, fac, y5, k7, c5, used32);
     return false;
 }
 
@@ -1341,20 +1388,34 @@ __device__ __forceinline__ unsigned long long lanemask_lt()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-static_assert(sizeof(Ray) <= SLOT_DOUBLES * sizeof(double), "parked ray state must fit a slot");
+static_assert(sizeof(Ray) % sizeof(double) == 0 && sizeof(GbsSearch) % sizeof(double) == 0, "parked in doubles");
+static_assert(sizeof(Ray) + sizeof(GbsSearch) <= SLOT_DOUBLES * sizeof(double), "parked ray state must fit a slot");
 
-__device__ __forceinline__ void park(const Ray& R, double* slot)
+// A lane's ray, and for the extrapolation its event search, to and from its slot.
+template <int METHOD>
+__device__ __forceinline__ void park(const Ray& R, const GbsSearch& S, double* slot)
 {
     const double* src = reinterpret_cast<const double*>(&R);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(Ray) / sizeof(double)); ++i) slot[i] = src[i];
+    if constexpr (METHOD == METHOD_GBS) {
+        const double* ss = reinterpret_cast<const double*>(&S);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(GbsSearch) / sizeof(double)); ++i) slot[sizeof(Ray) / sizeof(double) + i] = ss[i];
+    }
 }
 
-__device__ __forceinline__ void unpark(Ray& R, const double* slot)
+template <int METHOD>
+__device__ __forceinline__ void unpark(Ray& R, GbsSearch& S, const double* slot)
 {
     double* dst = reinterpret_cast<double*>(&R);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(Ray) / sizeof(double)); ++i) dst[i] = slot[i];
+    if constexpr (METHOD == METHOD_GBS) {
+        double* sd = reinterpret_cast<double*>(&S);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(GbsSearch) / sizeof(double)); ++i) sd[i] = slot[sizeof(Ray) / sizeof(double) + i];
+    }
 }
 
 // Serving: the rays of each job still to finish are counted down on the
@@ -1410,6 +1471,8 @@ trace_persistent(LaunchArgs A)
         D.job = s_job;
     }
     Ray R;
+    GbsSearch S;
+    S.phase = 0;
     bool active = false;
     bool parked = false;       // this lane used its step budget for this launch
     bool exhausted = false;
@@ -1417,7 +1480,7 @@ trace_persistent(LaunchArgs A)
     long long budget = A.step_budget;
     const long long slot = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (A.slots && A.slot_live[slot]) {
-        unpark(R, A.slots + slot * SLOT_DOUBLES);
+        unpark<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
         A.slot_live[slot] = 0u;
         active = !A.jobs[R.job].cancelled;
         if (!active) done = R.job;
@@ -1469,6 +1532,7 @@ trace_persistent(LaunchArgs A)
                         gid = A.first_ray + id;
                     }
                     active = ray_init<KIND>(R, gid, A, D, M);
+                    S.phase = 0;
                     if (!active) done = R.job;
                 }
                 if (A.remaining) count_done(A, done);
@@ -1479,11 +1543,11 @@ trace_persistent(LaunchArgs A)
             continue;
         }
         if (active) {
-            active = !ray_step<KIND, PREC, METHOD>(R, A, M);
+            active = !ray_step<KIND, PREC, METHOD>(R, S, A, M);
             if (!active) {
                 done = R.job;
             } else if (A.slots && --budget == 0) {
-                park(R, A.slots + slot * SLOT_DOUBLES);
+                park<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
                 A.slot_live[slot] = 1u;
                 active = false;
                 parked = true;
