@@ -239,6 +239,30 @@ int tartarus_trace_launch(const tartarus_metric* metric, const tartarus_camera* 
                           const tartarus_disk* disk, const tartarus_solver* solver,
                           const tartarus_outputs* out, const tartarus_launch* launch, void* hip_stream);
 
+/* Allocation-free trace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  As tartarus_trace_launch for the analytic Kerr metric, but the
+ * library's working memory for the call (job table, job constants, queue head,
+ * cost-order keys and counters, per-ray records) comes from one fixed array
+ * per device of TARTARUS_NOALLOC_SCRATCH_BYTES, which the library holds from
+ * its load until the process ends; the call itself allocates nothing (no
+ * hipMalloc, hipFree or pinned host memory) and copies the job table by
+ * kernel argument.  Limits: ncams <= TARTARUS_NOALLOC_MAX_CAMERAS and
+ * ncams * nx * ny <= TARTARUS_NOALLOC_MAX_RAYS (else TARTARUS_E_TOO_LARGE);
+ * metric kind TARTARUS_METRIC_KERR only (else TARTARUS_E_INVALID).  Every call
+ * on one device uses that device's one array, and a call leaves its contents
+ * behind: calls that overlap on a device (on two streams, or on one stream
+ * while another call's work is still running elsewhere) race and corrupt each
+ * other's results; calls in order on one stream are safe.  Not counted by
+ * tartarus_kernel_timing.  Results are bit-identical to tartarus_trace_launch
+ * with the same arguments (same kernels). */
+#define TARTARUS_NOALLOC_MAX_RAYS 262144
+#define TARTARUS_NOALLOC_MAX_CAMERAS 64
+#define TARTARUS_NOALLOC_SCRATCH_BYTES (135556096ull)   /* 129.3 MiB */
+int tartarus_trace_noalloc(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
+                           const tartarus_disk* disk, const tartarus_solver* solver,
+                           const tartarus_outputs* out, const tartarus_launch* launch, void* hip_stream);
+
 /* Time candidate launch shapes on the given trace (synchronously, on
  * hip_stream; each candidate is the best of three runs), keep the fastest for
  * this (metric kind, precision, method) for the rest of the process, and write

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtartarus.so")
-SOURCES = ["trace_kernel.hip", "aux_kernels.hip", "runtime.cpp", "host_logic.cpp"]
+SOURCES = ["trace_kernel.hip", "aux_kernels.hip", "noalloc.hip", "runtime.cpp", "host_logic.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions stay disabled (-packed-fp32-ops): some of their forms

@@ -120,5 +120,23 @@ struct LaunchArgs {
 
 constexpr int SLOT_DOUBLES = 40;   // a parked ray (31 doubles) and its event search (8)
 
+constexpr long long align256(long long b) { return (b + 255) / 256 * 256; }
+
+// Byte layout of the fixed working memory of the allocation-free trace
+// (tartarus_trace_noalloc): job table, job constants, queue head, cost-order
+// counters, keys and order, per-ray records; each part 256-byte aligned.
+struct NoallocLayout {
+    static constexpr long long max_rays = 262144;   // TARTARUS_NOALLOC_MAX_RAYS
+    static constexpr int max_cameras = 64;          // TARTARUS_NOALLOC_MAX_CAMERAS
+    static constexpr int buckets = 32;              // counters of the cost-ordered queue (kOrderBuckets)
+    static constexpr long long jobs = 0;
+    static constexpr long long jc = jobs + align256(max_cameras * (long long)sizeof(DevJob));
+    static constexpr long long head = jc + align256(max_cameras * (long long)sizeof(JobConst));
+    static constexpr long long count = head + 256;
+    static constexpr long long key = count + align256(2 * buckets * 4);
+    static constexpr long long order = key + align256(max_rays);
+    static constexpr long long rec = order + align256(4 * max_rays);
+    static constexpr long long bytes = rec + max_rays * REC_DOUBLES * 8;
+};
 
 }  // namespace tartarus

@@ -45,7 +45,8 @@ extern "C" hipError_t tartarus_launch_table_interleave(const LaunchArgs* args, d
 extern "C" hipError_t tartarus_launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_fill_u64(unsigned long long* p, unsigned long long v, long long n,
                                                hipStream_t stream);
-
+extern "C" hipError_t tartarus_noalloc_scratch(int device, void** ptr);
+extern "C" hipError_t tartarus_launch_job_upload(const DevJob* job, DevJob* dst, hipStream_t stream);
 
 namespace {
 
@@ -94,6 +95,7 @@ struct Device {
     // integrator timing (tartarus_kernel_timing): an event pair around each
     // integrator launch while on; pairs are read back by tartarus_kernel_time
     bool ktime_on = false;
+    unsigned char* scratch = nullptr;    // device address of the allocation-free trace's array
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ktime_pending, ktime_spare;
 };
 Device g_dev;
@@ -339,7 +341,11 @@ extern "C" int tartarus_init(int device, size_t hbm_budget_bytes)
         g_dev.budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)8 << 30;
         return TARTARUS_OK;
     }
+    // the allocation-free trace's working memory on this device (current now)
+    void* scratch = nullptr;
+    HIP_TRY(tartarus_noalloc_scratch(device, &scratch));
     g_dev.id = device;
+    g_dev.scratch = static_cast<unsigned char*>(scratch);
     g_dev.cus = prop.multiProcessorCount;
     g_dev.budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)8 << 30;
     g_dev.ready = true;
@@ -364,6 +370,45 @@ extern "C" int tartarus_trace(const tartarus_metric* metric, const tartarus_came
                               void* hip_stream)
 {
     return tartarus_trace_launch(metric, cams, ncams, disk, solver, out, nullptr, hip_stream);
+}
+
+static_assert(NoallocLayout::bytes == TARTARUS_NOALLOC_SCRATCH_BYTES, "header states the scratch size");
+static_assert(NoallocLayout::max_rays == TARTARUS_NOALLOC_MAX_RAYS, "header states the ray limit");
+static_assert(NoallocLayout::max_cameras == TARTARUS_NOALLOC_MAX_CAMERAS, "header states the camera limit");
+static_assert(NoallocLayout::buckets == kOrderBuckets, "cost-order counters");
+
+extern "C" int tartarus_trace_noalloc(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
+                                      const tartarus_disk* disk, const tartarus_solver* solver,
+                                      const tartarus_outputs* out, const tartarus_launch* launch, void* hip_stream)
+{
+    int rc = validate_all(metric, cams, ncams, disk, solver);
+    if (rc) return rc;
+    if ((rc = check_outputs(out))) return rc;
+    if (metric->kind != TARTARUS_METRIC_KERR)
+        return fail(TARTARUS_E_INVALID, "the allocation-free trace takes the analytic Kerr metric");
+    using NL = NoallocLayout;
+    if (ncams > NL::max_cameras) return fail(TARTARUS_E_TOO_LARGE, "more cameras than the allocation-free trace holds");
+    const long long per = (long long)cams[0].nx * cams[0].ny;
+    if (per * ncams > NL::max_rays) return fail(TARTARUS_E_TOO_LARGE, "more rays than the allocation-free trace holds");
+    std::lock_guard<std::mutex> lk(g_dev.mu);
+    if (!g_dev.ready || !g_dev.scratch) return fail(TARTARUS_E_DEVICE, "tartarus_init has not been called");
+    HIP_TRY(hipSetDevice(g_dev.id));
+    hipStream_t stream = (hipStream_t)hip_stream;
+    tartarus_launch L;
+    int grid = 0;
+    if ((rc = resolve_launch(metric->kind, kernel_precision(solver), solver->method, launch, L, grid, per * ncams)))
+        return rc;
+    unsigned char* b = g_dev.scratch;
+    TraceMem M{reinterpret_cast<DevJob*>(b + NL::jobs), reinterpret_cast<JobConst*>(b + NL::jc),
+               reinterpret_cast<unsigned long long*>(b + NL::head), reinterpret_cast<unsigned int*>(b + NL::order),
+               b + NL::key, reinterpret_cast<unsigned int*>(b + NL::count), nullptr};
+    double* rec = reinterpret_cast<double*>(b + NL::rec);
+    for (int c = 0; c < ncams; ++c) {
+        DevJob J;
+        fill_job(J, metric, cams[c], disk, solver, out, c * per, c * per, rec + (size_t)c * per * REC_DOUBLES);
+        HIP_TRY(tartarus_launch_job_upload(&J, M.djobs + c, stream));
+    }
+    return launch_sequence(metric, solver, L, grid, ncams, per, M, false, stream);
 }
 
 extern "C" int tartarus_build_kerr_table(double a, int nr, int nth, double r_min, double r_max, double* table,

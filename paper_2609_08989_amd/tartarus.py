@@ -85,6 +85,8 @@ def lib():
         L.tartarus_trace.argtypes = [P(Metric), P(Camera), C.c_int, P(Disk), P(Solver), P(Outputs), C.c_void_p]
         L.tartarus_trace_launch.argtypes = [P(Metric), P(Camera), C.c_int, P(Disk), P(Solver), P(Outputs),
                                             P(Launch), C.c_void_p]
+        L.tartarus_trace_noalloc.argtypes = [P(Metric), P(Camera), C.c_int, P(Disk), P(Solver), P(Outputs),
+                                             P(Launch), C.c_void_p]
         L.tartarus_autotune.argtypes = [P(Metric), P(Camera), C.c_int, P(Disk), P(Solver), P(Outputs),
                                         C.c_void_p, P(Launch)]
         L.tartarus_build_kerr_table.argtypes = [C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -195,6 +197,19 @@ def tartarus_trace(metric: Metric, cams, disk: Disk, solver: Solver, outputs: di
     else:
         _check(lib().tartarus_trace_launch(C.byref(metric), arr, len(cams), C.byref(disk), C.byref(solver),
                                            C.byref(so), C.byref(launch), _stream(stream)))
+
+
+def tartarus_trace_noalloc(metric: Metric, cams, disk: Disk, solver: Solver, outputs: dict, stream=None,
+                           launch: Launch | None = None) -> None:
+    cams = list(cams) if not isinstance(cams, Camera) else [cams]
+    arr = (Camera * len(cams))(*cams)
+    so = outputs_struct(outputs)
+    _check(lib().tartarus_trace_noalloc(C.byref(metric), arr, len(cams), C.byref(disk), C.byref(solver),
+                                        C.byref(so), C.byref(launch) if launch is not None else None,
+                                        _stream(stream)))
+
+
+NOALLOC_MAX_RAYS, NOALLOC_MAX_CAMERAS = 262144, 64
 
 
 def tartarus_autotune(metric: Metric, cams, disk: Disk, solver: Solver, outputs: dict, stream=None) -> Launch:

@@ -139,3 +139,24 @@ def test_null_outputs_rejected(T):
     m, c, d, s = good()
     arr = (T.Camera * 1)(c)
     assert T.lib().tartarus_trace(C.byref(m), arr, 1, C.byref(d), C.byref(s), None, None) == T.E_INVALID
+
+
+def test_noalloc_argument_errors_need_no_device(T):
+    """The allocation-free trace checks its limits before any device work: the
+    tabulated metric and over-size requests are refused with the right status."""
+    import workloads as W
+    w = W.WORKLOADS["kerr09_512"]
+    fake = T.Outputs(*([C.c_void_p(0x1000)] * len(T.OUTPUT_FIELDS)))
+    L = T.lib()
+    cam = T.make_camera(dict(w["cameras"][0], nx=513, ny=512))
+    args = (C.byref(T.make_metric(0.9)), (T.Camera * 1)(cam), 1, C.byref(T.make_disk(w["disk"])),
+            C.byref(T.make_solver(w["solver"])), C.byref(fake), None, None)
+    assert L.tartarus_trace_noalloc(*args) == T.E_TOO_LARGE
+    cams = (T.Camera * 65)(*([T.make_camera(dict(w["cameras"][0], nx=4, ny=4))] * 65))
+    assert L.tartarus_trace_noalloc(C.byref(T.make_metric(0.9)), cams, 65, C.byref(T.make_disk(w["disk"])),
+                                    C.byref(T.make_solver(w["solver"])), C.byref(fake), None, None) == T.E_TOO_LARGE
+    tab = T.Metric(T.METRIC_TABLE, 0.7, C.c_void_p(0x1000), 64, 32, 1.9, 2000.0)
+    small = (T.Camera * 1)(T.make_camera(dict(w["cameras"][0], nx=8, ny=8)))
+    assert L.tartarus_trace_noalloc(C.byref(tab), small, 1, C.byref(T.make_disk(w["disk"])),
+                                    C.byref(T.make_solver(w["solver"])), C.byref(fake), None, None) == T.E_INVALID
+    assert "analytic Kerr" in T.tartarus_last_error()
