@@ -35,7 +35,7 @@ extern "C" hipError_t tartarus_launch_trace(int kind, int prec, int method, cons
 extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_finish(const LaunchArgs* args, int job0, int njobs, long long max_rays,
                                             hipStream_t stream);
-extern "C" hipError_t tartarus_occupancy(int kind, int prec, int method, int block, int* blocks_per_cu);
+extern "C" hipError_t tartarus_occupancy(int kind, int prec, int method, int serve, int block, int* blocks_per_cu);
 extern "C" hipError_t tartarus_launch_build_table(double a, int nr, int nth, double r_min, double r_max,
                                                   double* table, hipStream_t stream);
 extern "C" hipError_t tartarus_launch_order(const LaunchArgs* args, long long total, unsigned char* key,
@@ -168,12 +168,12 @@ tartarus_launch default_launch(int kind, int prec, int method)
 // in host_logic.cpp); n_rays > 0 is a one-shot trace of that many rays.  The
 // caller holds g_dev.mu (the tuning table).
 int resolve_launch(int kind, int prec, int method, const tartarus_launch* req, tartarus_launch& L, int& grid,
-                   long long n_rays = 0)
+                   long long n_rays = 0, int serve = 0)
 {
     int rc = merge_shape(default_launch(kind, prec, method), req, L);
     if (rc) return rc;
     int occ = 0;
-    HIP_TRY(tartarus_occupancy(kind, prec, method, L.block_threads, &occ));
+    HIP_TRY(tartarus_occupancy(kind, prec, method, serve, L.block_threads, &occ));
     return finish_shape(L, occ, n_rays, g_dev.cus, grid);
 }
 
@@ -505,7 +505,7 @@ extern "C" int tartarus_autotune(const tartarus_metric* metric, const tartarus_c
             if (ms < best_ms) { best_ms = ms; cur = L; }
         }
         int occ = 0;
-        HIP_TRY(tartarus_occupancy(kind, prec, method, cur.block_threads, &occ));
+        HIP_TRY(tartarus_occupancy(kind, prec, method, 0, cur.block_threads, &occ));
         for (int bpc = 1; bpc <= occ; ++bpc) {
             tartarus_launch L = cur;
             L.blocks_per_cu = bpc;
@@ -705,7 +705,7 @@ int server_alloc(int prec, int method)
     {
         // the tuning table is shared with tartarus_autotune
         std::lock_guard<std::mutex> dlk(g_dev.mu);
-        int rc = resolve_launch(TARTARUS_METRIC_KERR, prec, method, nullptr, L, grid);
+        int rc = resolve_launch(TARTARUS_METRIC_KERR, prec, method, nullptr, L, grid, 0, 1);
         if (rc) return rc;
     }
     S.grid = grid;

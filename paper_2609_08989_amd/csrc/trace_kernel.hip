@@ -6,7 +6,7 @@
 //      (Sec. 2.2), r_+, the disk's inner edge and the Page-Thorne constants.
 //   2. order_keys / order_scan / order_scatter (traces of >= 4096 rays by
 //      default): the cost-ordered queue, rays nearest the critical curve first.
-//   3. trace_persistent<KIND, PREC, METHOD>: one lane integrates one ray at a
+//   3. trace_persistent<KIND, PREC, METHOD, SERVE>: one lane integrates one ray at a
 //      time.  A wavefront takes ray ids from a global atomic queue head; when
 //      a lane's ray terminates, the lane is refilled, so divergent step counts
 //      do not leave lanes idle until the slowest ray of the wave is done.  Per
@@ -1436,18 +1436,24 @@ __device__ __forceinline__ void count_done(const LaunchArgs& A, int& done)
     }
 }
 
-// Occupancy target: up to 256 VGPRs, at most 2 waves per SIMD.  One wave per
-// SIMD is usually fastest once the event roots are left to the finishing pass
-// (a lone wavefront keeps the long rays' critical path short); a second gives
-// the short rays more throughput.  The autotuner picks between the two.
-template <int KIND, int PREC, int METHOD>
+// SERVE = 1: the serving epochs' instance, which resumes parked rays, parks
+// those that use up the epoch's attempt budget and counts finished rays down per
+// request; SERVE = 0: one-shot traces, without that machinery (a ray that can
+// be parked at any iteration keeps every field of its state live, 190 VGPRs
+// against 160 for the Dormand-Prince FP64 instance).
+//
+// Occupancy target: at most 2 waves per SIMD (up to 256 VGPRs), or 3 (168) for
+// the one-shot instances that fit it without spills.  One wave per SIMD is
+// fastest on small images (a lone wavefront keeps the long rays' critical path
+// short); more give large images more throughput.  The autotuner picks.
+template <int KIND, int PREC, int METHOD, int SERVE>
 struct WavesPerEU {
-    static constexpr int value = 2;
+    static constexpr int value = (!SERVE && KIND == 0 && PREC == 0 && METHOD == METHOD_DP45) ? 3 : 2;
 };
 
-template <int KIND, int PREC, int METHOD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<KIND, PREC, METHOD>::value)))
-trace_persistent(LaunchArgs A)
+template <int KIND, int PREC, int METHOD, int SERVE>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(WavesPerEU<KIND, PREC, METHOD, SERVE>::value))) trace_persistent(LaunchArgs A)
 {
     MetricOps<KIND> M;
     if (KIND == 1) {
@@ -1479,13 +1485,15 @@ trace_persistent(LaunchArgs A)
     int done = -1;             // serving: job of a ray that ended this iteration
     long long budget = A.step_budget;
     const long long slot = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (A.slots && A.slot_live[slot]) {
-        unpark<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
-        A.slot_live[slot] = 0u;
-        active = !A.jobs[R.job].cancelled;
-        if (!active) done = R.job;
+    if constexpr (SERVE) {
+        if (A.slots && A.slot_live[slot]) {
+            unpark<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
+            A.slot_live[slot] = 0u;
+            active = !A.jobs[R.job].cancelled;
+            if (!active) done = R.job;
+        }
+        if (A.remaining) count_done(A, done);
     }
-    if (A.remaining) count_done(A, done);
     // this wavefront's current chunk of ray ids [next, end) (wave-uniform values)
     long long next = 0, end = 0;
     const long long n_rays = A.total_rays - A.first_ray;
@@ -1506,7 +1514,7 @@ trace_persistent(LaunchArgs A)
                     // refills.  In serving epochs a wavefront may exit with all
                     // lanes parked, so it fetches exactly the ids it hands out:
                     // an id taken from the queue is never left unassigned.
-                    const long long fetch = A.slots ? (long long)rem : (A.chunk > rem ? A.chunk : rem);
+                    const long long fetch = (SERVE && A.slots) ? (long long)rem : (A.chunk > rem ? A.chunk : rem);
                     const int leader = __ffsll((long long)need) - 1;
                     unsigned long long c0 = 0;
                     if ((int)__lane_id() == leader) c0 = atomicAdd(A.head, (unsigned long long)fetch);
@@ -1535,7 +1543,9 @@ trace_persistent(LaunchArgs A)
                     S.phase = 0;
                     if (!active) done = R.job;
                 }
-                if (A.remaining) count_done(A, done);
+                if constexpr (SERVE) {
+                    if (A.remaining) count_done(A, done);
+                }
             }
         }
         if (!__any(active)) {
@@ -1546,14 +1556,16 @@ trace_persistent(LaunchArgs A)
             active = !ray_step<KIND, PREC, METHOD>(R, S, A, M);
             if (!active) {
                 done = R.job;
-            } else if (A.slots && --budget == 0) {
+            } else if (SERVE && A.slots && --budget == 0) {
                 park<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
                 A.slot_live[slot] = 1u;
                 active = false;
                 parked = true;
             }
         }
-        if (A.remaining) count_done(A, done);
+        if constexpr (SERVE) {
+            if (A.remaining) count_done(A, done);
+        }
     }
 }
 
@@ -1785,30 +1797,41 @@ extern "C" hipError_t tartarus_launch_setup(int kind, const LaunchArgs* args, hi
 // is none.  Mixed precision and the tabulated metric are provided with
 // Dormand-Prince only (a tabulated six-stage instance keeps all six stage
 // derivatives next to the table patch and spills heavily).
-static const void* trace_kernel_for(int kind, int prec, int method)
+static const void* trace_kernel_for(int kind, int prec, int method, int serve)
 {
-    if (kind == 0 && prec == 0 && method == 0) return (const void*)trace_persistent<0, 0, 0>;
-    if (kind == 0 && prec == 0 && method == 1) return (const void*)trace_persistent<0, 0, 1>;
-    if (kind == 0 && prec == 0 && method == 2) return (const void*)trace_persistent<0, 0, 2>;
-    if (kind == 0 && prec == 1 && method == 0) return (const void*)trace_persistent<0, 1, 0>;
-    if (kind == 0 && prec == 0 && method == 3) return (const void*)trace_persistent<0, 0, 3>;
-    if (kind == 0 && prec == 0 && method == 4) return (const void*)trace_persistent<0, 0, 4>;
-    if (kind == 1 && prec == 0 && method == 0) return (const void*)trace_persistent<1, 0, 0>;
+    if (serve) {
+        // serving takes analytic Kerr requests
+        if (kind == 0 && prec == 0 && method == 0) return (const void*)trace_persistent<0, 0, 0, 1>;
+        if (kind == 0 && prec == 0 && method == 1) return (const void*)trace_persistent<0, 0, 1, 1>;
+        if (kind == 0 && prec == 0 && method == 2) return (const void*)trace_persistent<0, 0, 2, 1>;
+        if (kind == 0 && prec == 1 && method == 0) return (const void*)trace_persistent<0, 1, 0, 1>;
+        if (kind == 0 && prec == 0 && method == 3) return (const void*)trace_persistent<0, 0, 3, 1>;
+        if (kind == 0 && prec == 0 && method == 4) return (const void*)trace_persistent<0, 0, 4, 1>;
+        return nullptr;
+    }
+    if (kind == 0 && prec == 0 && method == 0) return (const void*)trace_persistent<0, 0, 0, 0>;
+    if (kind == 0 && prec == 0 && method == 1) return (const void*)trace_persistent<0, 0, 1, 0>;
+    if (kind == 0 && prec == 0 && method == 2) return (const void*)trace_persistent<0, 0, 2, 0>;
+    if (kind == 0 && prec == 1 && method == 0) return (const void*)trace_persistent<0, 1, 0, 0>;
+    if (kind == 0 && prec == 0 && method == 3) return (const void*)trace_persistent<0, 0, 3, 0>;
+    if (kind == 0 && prec == 0 && method == 4) return (const void*)trace_persistent<0, 0, 4, 0>;
+    if (kind == 1 && prec == 0 && method == 0) return (const void*)trace_persistent<1, 0, 0, 0>;
     return nullptr;
 }
 
+// The serving instance runs when the launch parks rays (args->slots).
 extern "C" hipError_t tartarus_launch_trace(int kind, int prec, int method, const LaunchArgs* args, int grid,
                                             int block, hipStream_t stream)
 {
-    const void* f = trace_kernel_for(kind, prec, method);
+    const void* f = trace_kernel_for(kind, prec, method, args->slots != nullptr);
     if (!f) return hipErrorInvalidValue;
     void* params[] = {(void*)args};
     return hipLaunchKernel(f, dim3(grid), dim3(block), params, 0, stream);
 }
 
-extern "C" hipError_t tartarus_occupancy(int kind, int prec, int method, int block, int* blocks_per_cu)
+extern "C" hipError_t tartarus_occupancy(int kind, int prec, int method, int serve, int block, int* blocks_per_cu)
 {
-    const void* f = trace_kernel_for(kind, prec, method);
+    const void* f = trace_kernel_for(kind, prec, method, serve);
     if (!f) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, 0);
 }
