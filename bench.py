@@ -486,11 +486,11 @@ def main():
                             "(FMA = 2), over this run's kernel time"}
         traffic = float(cnt["fetch_bytes"] + cnt["write_bytes"])
         occupancy = {"mean_resident_waves_per_simd": cnt.get("mean_resident_waves_per_simd"),
+                     "max_waves_per_simd": cnt.get("max_waves_per_simd"), "vgprs": cnt.get("vgprs"),
                      "counter_launch_shape": cnt.get("launch"), "counter_rtol": cnt.get("rtol")}
     if launch is not None:
         sh = dict(zip(SHAPE_KEYS, shape(launch)))
-        occupancy = dict(occupancy or {}, launched_waves_per_simd=sh["block_threads"] // 64 * sh["blocks_per_cu"] / 4.0,
-                         max_waves_per_simd=2)
+        occupancy = dict(occupancy or {}, launched_waves_per_simd=sh["block_threads"] // 64 * sh["blocks_per_cu"] / 4.0)
     result = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,

@@ -40,25 +40,34 @@ struct DevJob {
     double event_tol;               // event location tolerance (affine parameter)
 };
 
-// Per-ray record the integrator leaves for the finishing pass (doubles).
-// Crossing slot k (k < 3) at REC_SLOT_LEN * k: r0, kr0, r1, kr1, th0, kth0, th1,
-// kth1, h, lam, cos(th0) of the step that crossed the equator on the disk (h = 0:
-// already located, r0 = radius, lam = affine parameter of the crossing).
+// Per-ray record the integrator leaves for the finishing pass (doubles).  The
+// fields every ray needs come first, in REC_HEAD doubles (192 bytes, within
+// the record's first two 128-byte lines), so the finishing pass reads them as
+// one contiguous run; the hit slots follow and are read only for rays that
+// hit the disk.
 // Terminal step at REC_TERM: r, th, phi as (y0, dy0/dlam, y1, dy1/dlam) each,
 // then h, lam, target radius, cos(th0); for rays that end without a terminal
 // root (failed) only the three y0 are meaningful.  REC_CODE: terminal kind
 // (0 none, 1 horizon, 2 escape) + 4 if the equator was crossed in that step,
 // or 8: the step's equatorial crossing is on an opaque disk and ends the ray.
 // REC_INTS: int32 cls, n_hits, n_accept, n_reject, n_fp32, n_cross, order[3].
+// Crossing slot k (k < 3) at REC_SLOT0 + REC_SLOT_LEN * k: r0, kr0, r1, kr1,
+// th0, kth0, th1, kth1, h, lam, cos(th0) of the step that crossed the equator
+// on the disk (h = 0: already located, r0 = radius, lam = affine parameter of
+// the crossing).
 constexpr int DISK_OPAQUE = 1;     // the first crossing on the disk ends the ray
 constexpr int DISK_INTRINSIC = 2;  // hit flux F instead of g^4 F
+constexpr int REC_TERM = 0;
+constexpr int REC_CODE = 16;
+constexpr int REC_HMAX = 17;
+constexpr int REC_HGATE = 18;
+constexpr int REC_INTS = 19;       // 9 int32 in doubles 19..23
+constexpr int REC_HEAD = 24;
+constexpr int REC_SLOT0 = REC_HEAD;
 constexpr int REC_SLOT_LEN = 11;
-constexpr int REC_TERM = 33;
-constexpr int REC_CODE = 49;
-constexpr int REC_HMAX = 50;
-constexpr int REC_HGATE = 51;
-constexpr int REC_INTS = 52;
-constexpr int REC_DOUBLES = 64;
+constexpr int REC_DOUBLES = 64;    // 512 bytes: records stay aligned to 128-byte lines
+static_assert(REC_SLOT0 + 3 * REC_SLOT_LEN <= REC_DOUBLES, "record overflow");
+static_assert(REC_HEAD % 2 == 0, "the header is read in 16-byte pieces");
 
 // Per-job constants computed on the device by the set-up kernel before a
 // trace: the observer's metric and ZAMO tetrad (Sec. 2.2), the horizon

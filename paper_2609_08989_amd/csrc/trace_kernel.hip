@@ -509,7 +509,7 @@ __device__ __forceinline__ void disk_crossing(Ray& R, double h, const Deriv<doub
     const double lo = fmin(fmin(R.r, y5.r), fmin(b1, b2)), hi = fmax(fmax(R.r, y5.r), fmax(b1, b2));
     constexpr double m = 1e-12;   // margin for rounding of the cubic evaluated at the root
     if (hi < R.r_in * (1.0 - m) || lo > R.r_out * (1.0 + m)) return;
-    double* sl = R.rec + REC_SLOT_LEN * R.n_hits;
+    double* sl = R.rec + REC_SLOT0 + REC_SLOT_LEN * R.n_hits;
     if (lo >= R.r_in * (1.0 + m) && hi <= R.r_out * (1.0 - m)) {
         sl[0] = R.r;
         sl[1] = R.k.r;
@@ -1205,7 +1205,7 @@ __device__ bool gbs_probe(Ray& R, GbsSearch& S, const LaunchArgs& A, const Deriv
     if (!terminal || S.s <= term[13]) {
         R.n_cross++;
         if (y.r >= R.r_in && y.r <= R.r_out && R.n_hits < R.max_hits) {
-            double* sl = R.rec + REC_SLOT_LEN * R.n_hits;
+            double* sl = R.rec + REC_SLOT0 + REC_SLOT_LEN * R.n_hits;
             sl[0] = y.r;
             sl[8] = 0.0;
             sl[9] = fma(S.s, S.h, R.lam);
@@ -1572,6 +1572,14 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // finishing pass: event roots, outputs, and shading (g and g^4 F(r))
 // ---------------------------------------------------------------------------
+// int32 field i of a record header held in registers (REC_INTS: two per
+// double, the lower address in the low half).
+__device__ __forceinline__ int rec_int(const double* hd, int i)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(hd[REC_INTS + (i >> 1)]);
+    return (int)(unsigned)((i & 1) ? (b >> 32) : b);
+}
+
 // One thread per ray.  Locates the crossings and the terminal root the
 // integrator left in the ray's record (same cubics and root finders as on the
 // integrator side, so the results do not depend on where a root was found),
@@ -1586,16 +1594,25 @@ __global__ void finish_kernel(const DevJob* jobs, const JobConst* jc, int job0)
     if (J.cancelled) return;
     const JobConst& C = jc[jb];
     const double* rec = J.rec + q * REC_DOUBLES;
-    const int* iv = reinterpret_cast<const int*>(rec + REC_INTS);
+    // the header as one run of 16-byte loads issued together, so each of its
+    // two lines is fetched once (reads spread over the code below would let
+    // other waves evict a line between them)
+    double hd[REC_HEAD];
+#pragma unroll
+    for (int i = 0; i < REC_HEAD; i += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(rec + i);
+        hd[i] = v.x;
+        hd[i + 1] = v.y;
+    }
     const double tol = 0.125 * J.event_tol;
-    int n = iv[1];
-    int n_cross = iv[5];
+    int n = rec_int(hd, 1);
+    int n_cross = rec_int(hd, 5);
     double hr[3] = {0.0, 0.0, 0.0}, hl[3] = {0.0, 0.0, 0.0};
     int ho[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (k >= n) break;
-        const double* sl = rec + REC_SLOT_LEN * k;
+        const double* sl = rec + REC_SLOT0 + REC_SLOT_LEN * k;
         if (sl[8] > 0.0) {
             const double h = sl[8];
             const Cubic pth(sl[4], sl[5], sl[6], sl[7], h);
@@ -1606,11 +1623,11 @@ __global__ void finish_kernel(const DevJob* jobs, const JobConst* jc, int job0)
             hr[k] = sl[0];
             hl[k] = sl[9];
         }
-        ho[k] = iv[6 + k];
+        ho[k] = rec_int(hd, 6 + k);
     }
-    const double* t = rec + REC_TERM;
-    const int code = (int)rec[REC_CODE];
-    int cls = iv[0];
+    const double* t = hd + REC_TERM;
+    const int code = (int)hd[REC_CODE];
+    int cls = rec_int(hd, 0);
     double fr = t[0], fth = t[4], fph = t[8];
     if (code & 11) {
         const double h = t[12];
@@ -1656,11 +1673,11 @@ __global__ void finish_kernel(const DevJob* jobs, const JobConst* jc, int job0)
     J.final_rtp[3 * q + 0] = fr;
     J.final_rtp[3 * q + 1] = fth;
     J.final_rtp[3 * q + 2] = fph;
-    J.h_drift[q] = rec[REC_HMAX];
-    J.h_gate[q] = rec[REC_HGATE];
-    J.n_accept[q] = iv[2];
-    J.n_reject[q] = iv[3];
-    J.n_fp32[q] = iv[4];
+    J.h_drift[q] = hd[REC_HMAX];
+    J.h_gate[q] = hd[REC_HGATE];
+    J.n_accept[q] = rec_int(hd, 2);
+    J.n_reject[q] = rec_int(hd, 3);
+    J.n_fp32[q] = rec_int(hd, 4);
     J.n_cross[q] = n_cross;
     double inten = 0.0;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
