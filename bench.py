@@ -47,6 +47,8 @@ GATE_RTOLS = (1e-8, 3e-9, 1e-9, 3e-10, 1e-10)
 GATE_RTOLS_BEYOND = (3e-11, 1e-11)   # searched only when no listed tolerance passes
 GATE_H = 1e-8
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+GATHER_BYTES_PER_RHS = 640
+PEAK_L2_TBS = 8 * 16 * 128 * 2.4e9 / 1e12   # 39.3 TB/s, derived from the L2 organisation
 PEAK_FP32_TFLOPS = 78.6     # non-packed FP32 (packed FP32 is disabled in this build)
 
 # Algorithmic FLOPs (FMA = 2, division / sqrt / transcendental = 1) of the
@@ -226,6 +228,19 @@ def leg_record(T, torch, S, la, steps, warmup, launch=None, extra=None) -> dict:
     return rec
 
 
+def gather_roofline(rec: dict, n_rays: int) -> dict:
+    """Table bytes the tabulated integrator gathers per second: 640 B per
+    right-hand side (2 x 2 nodes x 5 components x 4 doubles), six right-hand
+    sides per attempt and one per ray, over the integrator's launch time.  The
+    gathers are served by L2 (94 % hits in the tabulated-kernel profile); the
+    peak is the L2 read bandwidth of 8 XCDs x 16 channels x 128 B per clock at
+    2.4 GHz."""
+    rhs = rec["attempts_per_ray"] * n_rays * 6 + n_rays
+    achieved = rhs * GATHER_BYTES_PER_RHS / (rec["kernel_ms"] * 1e-3) / 1e12
+    return {"bound": "l2", "achieved": achieved, "peak": PEAK_L2_TBS, "unit": "TB/s", "frac": achieved / PEAK_L2_TBS,
+            "bytes_per_rhs": GATHER_BYTES_PER_RHS, "rhs_per_launch": rhs}
+
+
 def gate_search(T, S, prec):
     """Untimed traces at each listed tolerance: the gate per tolerance and the
     loosest tolerance whose gate holds; when none of the listed ones does, the
@@ -277,7 +292,9 @@ def workload_legs(T, torch, W, steps, autotune: bool) -> dict:
         del S
     S, launch = tabulated_scene(T, torch, W)
     log("bench: workload tabulated07_64cams")
-    legs["tabulated07_64cams"] = leg_record(T, torch, S, S.args(), 2, 1, launch)
+    rec = leg_record(T, torch, S, S.args(), 2, 1, launch)
+    rec["gather_roofline"] = gather_roofline(rec, S.n)
+    legs["tabulated07_64cams"] = rec
     return legs
 
 
