@@ -34,14 +34,23 @@
  *     with increasing lambda (same spatial path; g is unchanged);
  *   - step control: RMS norm over the 8 components with scale atol + rtol *
  *     max(|y_n|, |y_n+1|); accept iff err <= 1 (NaN rejects); new step
- *     h * min(fmax, max(0.2, 0.9 err^-1/5)), fmax = 10, or 1 right after a
- *     rejection; first step h0_frac * r_obs;
+ *     h * min(fmax, max(0.2, 0.9 err^(-1/p))), p = 5 for the 5(4) pairs and
+ *     11 for the extrapolation, fmax = 10, or 1 right after a rejection; first
+ *     step h0_frac * r_obs.  A component whose error estimate lies within its
+ *     own rounding (2^18 ulps of h |b - b*|_1 max(|k_n|, |k_n+1|) for a pair,
+ *     of the largest sweep increment for the extrapolation, capped at 1 % of
+ *     the component's tolerance scale) counts as zero, so that step sequences
+ *     do not depend on rounding order; the extrapolation's step factor is
+ *     rounded down to a power of two;
  *   - events on each accepted step: horizon when r falls to horizon_factor *
  *     r_+ (or the table's inner radius, if larger), escape when r rises to
  *     r_escape, disk crossing when cos(theta) changes sign; the root is
- *     located on the interpolant to well within event_tol in lambda
- *     (safeguarded Newton iteration on the cubic, bracket kept; the paper
- *     bisects to ~1e-12, and the two roots differ by less than that);
+ *     located on the step's cubic Hermite interpolant to well within
+ *     event_tol in lambda (safeguarded Newton iteration on the cubic, bracket
+ *     kept; the paper bisects to ~1e-12, and the two roots differ by less than
+ *     that); for the extrapolation, whose macro-steps are too long for a cubic,
+ *     on the method's own solution (sub-steps re-integrated from the step's
+ *     start, the cubic's root as first guess);
  *   - emitter: prograde Keplerian Omega = 1 / (r^{3/2} + a); the first up to
  *     max_hits (<= 3) crossings inside [r_in, r_out] are recorded; the ray
  *     continues to a terminal event unless the disk is opaque.
@@ -127,16 +136,21 @@ typedef struct {
 /* Integrator settings (Sec. 3.2).  rtol > 0, atol > 0, h0_frac > 0,
  * horizon_factor >= 1, r_obs < r_escape <= 1e15, event_tol > 0, max_steps >= 1
  * (attempted steps, accepted + rejected).  precision: TARTARUS_PREC_FP64, or
- * TARTARUS_PREC_MIXED (Runge-Kutta stages evaluated in FP32 in the far field;
- * state sums, error norm, controller, events and shading stay FP64).
+ * TARTARUS_PREC_MIXED (Runge-Kutta stages evaluated in FP32 in the far field,
+ * r >= 10 r_+ away from turning points and the axis, on steps whose FP32
+ * rounding stays below half the tolerance: h |k_i| <= 2.6e7 (atol + rtol |y_i|)
+ * for every component; state sums, error norm, controller, events and shading
+ * stay FP64.  Below rtol 5e-10 no far-field step passes that test, and a mixed
+ * trace runs the FP64 arithmetic throughout, n_fp32 = 0).
  * method (Sec. 3.2): an embedded 5(4) pair, TARTARUS_METHOD_DP45
  * (Dormand-Prince), TARTARUS_METHOD_CK45 (Cash-Karp) or TARTARUS_METHOD_RKF45
  * (Fehlberg), each propagating the fifth-order solution with the step
  * controlled by the embedded fourth-order estimate; or TARTARUS_METHOD_GBS,
  * Gragg-Bulirsch-Stoer extrapolation: per macro-step six modified-midpoint
  * sweeps with 2, 4, ..., 12 substeps, Richardson extrapolation in h^2 to order
- * 12, the difference to the order-10 entry as error estimate (42 right-hand
- * sides per attempt, against 6 for a pair); or TARTARUS_METHOD_VERLET, the
+ * 12 of the sweeps' increments y - y_n, the difference to the order-10 entry
+ * as error estimate (42 right-hand sides per attempt, against 6 for a pair);
+ * or TARTARUS_METHOD_VERLET, the
  * symmetric, symplectic generalized Stormer-Verlet scheme with the FIXED step
  * h0_frac * r_obs and no error control (rtol and atol are not used; every
  * step counts as accepted).  Its two implicit stages are solved by fixed-point
@@ -147,9 +161,8 @@ typedef struct {
  * 1e5-1e6 steps per ray from a distant camera; with horizon_factor >= 1.05
  * the captured rays of a spin-0.9 hole reach the stop radius at h <= 0.01.
  * For every method, h0_frac and max_steps keep their meaning (an attempt is
- * one macro-step or one fixed step), and events are located on the cubic
- * Hermite interpolant of the accepted step.  Mixed precision and the
- * tabulated metric need DP45. */
+ * one macro-step or one fixed step), and events are located as described at
+ * the top of this file.  Mixed precision and the tabulated metric need DP45. */
 enum {
     TARTARUS_METHOD_DP45 = 0,
     TARTARUS_METHOD_CK45 = 1,
@@ -258,7 +271,7 @@ int tartarus_trace_launch(const tartarus_metric* metric, const tartarus_camera* 
  * with the same arguments (same kernels). */
 #define TARTARUS_NOALLOC_MAX_RAYS 262144
 #define TARTARUS_NOALLOC_MAX_CAMERAS 64
-#define TARTARUS_NOALLOC_SCRATCH_BYTES (135556096ull)   /* 129.3 MiB */
+#define TARTARUS_NOALLOC_SCRATCH_BYTES (135559680ull)   /* 129.3 MiB */
 int tartarus_trace_noalloc(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
                            const tartarus_disk* disk, const tartarus_solver* solver,
                            const tartarus_outputs* out, const tartarus_launch* launch, void* hip_stream);
@@ -296,10 +309,11 @@ int tartarus_build_kerr_table(double a, int nr, int nth, double r_min, double r_
  * their output bytes plus the library's ray-slot arena fit the HBM budget,
  * and traces all admitted requests together on one device queue in epochs;
  * requests arriving while others run join at the next epoch.  Per-ray results
- * are bit-identical to tartarus_trace of the same request alone.  The solver
- * of the first request fixes rtol/atol/... for the session; later requests
- * must use the same solver (else E_INVALID).  Output buffers must stay alive
- * until poll reports done or cancel returns. */
+ * are bit-identical to tartarus_trace of the same request alone.  Tolerances,
+ * step settings and precision are the request's own; the integration method
+ * is the session's (the first request's: a request with another method gets
+ * E_INVALID).  Output buffers must stay alive until poll reports done or
+ * cancel returns. */
 
 /* Hand-out order of the serving queue's unstarted rays, applied from the next
  * epoch on: TARTARUS_SERVE_SMALLEST_FIRST (default) gives lanes to the rays of

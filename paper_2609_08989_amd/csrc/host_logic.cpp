@@ -161,6 +161,13 @@ void fill_job(DevJob& J, const tartarus_metric* m, const tartarus_camera& c, con
     J.remaining = nullptr;
     J.rec = rec;
     J.event_tol = s->event_tol;
+    J.rtol = s->rtol;
+    J.atol = s->atol;
+    J.h0_frac = s->h0_frac;
+    J.horizon_factor = s->horizon_factor;
+    J.r_escape = s->r_escape;
+    J.max_steps = s->max_steps;
+    J.allow32 = kernel_precision(s) == TARTARUS_PREC_MIXED ? 1 : 0;
 }
 
 void fill_args(LaunchArgs& A, const tartarus_metric* m, const tartarus_solver* s)

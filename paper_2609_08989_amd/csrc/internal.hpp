@@ -38,6 +38,12 @@ struct DevJob {
     int pad1;
     double* rec;                    // [ray_count][REC_DOUBLES] integrator -> finishing pass records
     double event_tol;               // event location tolerance (affine parameter)
+    // the request's solver settings (serving traces each ray with its own
+    // request's; a one-shot trace's kernels take them from the launch)
+    double rtol, atol, h0_frac, horizon_factor, r_escape;
+    long long max_steps;
+    int allow32;                    // mixed precision: FP32 stages allowed (tolerance permitting)
+    int pad2;
 };
 
 // Per-ray record the integrator leaves for the finishing pass (doubles).  The

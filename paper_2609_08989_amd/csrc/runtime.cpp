@@ -901,6 +901,11 @@ int server_round(std::unique_lock<std::mutex>& lk)
     }
     const long long total = S.hseg_q[nseg];
     const tartarus_solver sv = S.solver;
+    // the mixed-precision instance when a live request may use FP32 stages;
+    // its FP64 path traces the other requests with the FP64 instance's arithmetic
+    int eprec = TARTARUS_PREC_FP64;
+    for (int e = 0; e < kMaxEntries; ++e)
+        if (S.entry_ticket[e] && !S.hjobs[e].cancelled && S.hjobs[e].allow32) eprec = TARTARUS_PREC_MIXED;
     lk.unlock();
 
     HIP_TRY(hipMemcpyAsync(S.djobs, S.hjobs, sizeof(DevJob) * kMaxEntries, hipMemcpyHostToDevice, S.stream));
@@ -940,7 +945,7 @@ int server_round(std::unique_lock<std::mutex>& lk)
     A.ndir = nd;
     A.remaining = S.dremaining;
     if (!fresh.empty()) HIP_TRY(tartarus_launch_setup(TARTARUS_METRIC_KERR, &A, S.stream));
-    HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, kernel_precision(&sv), sv.method, &A, S.grid, S.block, S.stream));
+    HIP_TRY(tartarus_launch_trace(TARTARUS_METRIC_KERR, eprec, sv.method, &A, S.grid, S.block, S.stream));
     HIP_TRY(hipMemcpyAsync(S.hremaining, S.dremaining, sizeof(unsigned int) * kMaxEntries, hipMemcpyDeviceToHost,
                            S.stream));
     HIP_TRY(hipMemcpyAsync(S.hhead, S.dhead, sizeof(unsigned long long), hipMemcpyDeviceToHost, S.stream));
@@ -970,7 +975,10 @@ void server_main()
     Server& S = g_srv;
     std::unique_lock<std::mutex> lk(S.mu);
     if (!S.dev_ready) {
-        int rc = server_alloc(kernel_precision(&S.solver), S.solver.method);
+        // the launch shape must suit both serving instances an epoch may run
+        // (mixed precision needs at least the FP64 instance's registers)
+        const int prec = S.solver.method == TARTARUS_METHOD_DP45 ? TARTARUS_PREC_MIXED : TARTARUS_PREC_FP64;
+        int rc = server_alloc(prec, S.solver.method);
         if (rc) {
             S.dev_error = tartarus_last_error();
             S.running = false;
@@ -993,12 +1001,7 @@ void server_main()
     }
 }
 
-bool same_solver(const tartarus_solver& a, const tartarus_solver& b)
-{
-    return a.rtol == b.rtol && a.atol == b.atol && a.h0_frac == b.h0_frac && a.horizon_factor == b.horizon_factor &&
-           a.r_escape == b.r_escape && a.event_tol == b.event_tol && a.max_steps == b.max_steps &&
-           a.precision == b.precision && a.method == b.method;
-}
+
 
 }  // namespace
 
@@ -1024,8 +1027,8 @@ extern "C" int tartarus_submit(const tartarus_metric* metric, const tartarus_cam
     Server& S = g_srv;
     std::unique_lock<std::mutex> lk(S.mu);
     if (!S.dev_error.empty()) return fail(TARTARUS_E_DEVICE, "serving stopped after a device error: " + S.dev_error);
-    if (S.have_solver && !same_solver(S.solver, *solver))
-        return fail(TARTARUS_E_INVALID, "requests of one serving session must share the solver settings");
+    if (S.have_solver && S.solver.method != solver->method)
+        return fail(TARTARUS_E_INVALID, "requests of one serving session must share the integration method");
     Request R;
     R.metric = *metric;
     R.cam = *cam;

@@ -138,6 +138,26 @@ struct Ray {
     double r_in, r_out;  // disk radii
 };
 
+// Solver settings a ray is traced with.  A one-shot trace takes them from the
+// launch (every ray of the trace shares them, so they stay wave-uniform); a
+// serving epoch takes each ray's from its request, so requests of different
+// tolerances and precisions share the epoch.
+struct RaySettings {
+    double rtol, atol, horizon_factor, r_escape, event_tol;
+    long long max_steps;
+    int allow32;   // mixed precision: FP32 stages allowed where the regime test passes
+};
+
+__device__ __forceinline__ RaySettings launch_settings(const LaunchArgs& A)
+{
+    return {A.rtol, A.atol, A.horizon_factor, A.r_escape, A.event_tol, A.max_steps, 1};
+}
+
+__device__ __forceinline__ RaySettings job_settings(const DevJob& J)
+{
+    return {J.rtol, J.atol, J.horizon_factor, J.r_escape, J.event_tol, J.max_steps, J.allow32};
+}
+
 template <int KIND>
 struct MetricOps {
     TableView T;
@@ -400,7 +420,7 @@ __device__ bool ray_init(Ray& R, long long gid, const LaunchArgs& A, const JobDi
     R.hmax = fabs(H);
     R.hgate = R.r >= 1.5 * R.rp ? fabs(H) : 0.0;
     R.lam = 0.0;
-    R.h = A.h0_frac * J.r_obs;
+    R.h = J.h0_frac * J.r_obs;
     R.n_acc = R.n_rej = R.n_f32 = R.n_cross = R.n_hits = R.rej_prev = 0;
     R.max_hits = J.max_hits;
     R.opaque = J.disk_flags & DISK_OPAQUE;
@@ -564,10 +584,10 @@ __device__ __forceinline__ bool fp32_noise_ok(double hk, double y, double atol, 
     return fabs(hk) <= kNoiseRatio * fma(rtol, fabs(y), atol);
 }
 
-__device__ __forceinline__ bool far_field(const Ray& R, const LaunchArgs& A)
+__device__ __forceinline__ bool far_field(const Ray& R, const LaunchArgs& A, const RaySettings& P)
 {
-    const double h = R.h, atol = A.atol, rtol = A.rtol;
-    return R.r >= A.r_switch_factor * R.rp && R.cth * R.cth <= 0.99 && fabs(R.pr) >= (double)R.guard_r &&
+    const double h = R.h, atol = P.atol, rtol = P.rtol;
+    return P.allow32 && R.r >= A.r_switch_factor * R.rp && R.cth * R.cth <= 0.99 && fabs(R.pr) >= (double)R.guard_r &&
            fabs(R.pth) >= (double)R.guard_th && fp32_noise_ok(h * R.k.r, R.r, atol, rtol) &&
            fp32_noise_ok(h * R.k.th, R.th, atol, rtol) && fp32_noise_ok(h * R.k.ph, R.ph, atol, rtol) &&
            fp32_noise_ok(h * R.k.pr, R.pr, atol, rtol) && fp32_noise_ok(h * R.k.pth, R.pth, atol, rtol);
@@ -1153,7 +1173,8 @@ __device__ __forceinline__ void advance(Ray& R, double h, double fac, const Deri
 
 // One probe of an event search, with the solution y at s and its slope k.
 // Returns true when the ray has ended.
-__device__ bool gbs_probe(Ray& R, GbsSearch& S, const LaunchArgs& A, const Deriv<double>& y, const Deriv<double>& k,
+__device__ bool gbs_probe(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySettings& P, const Deriv<double>& y,
+                          const Deriv<double>& k,
                           double c)
 {
     if (S.phase == 3) {
@@ -1179,7 +1200,7 @@ __device__ bool gbs_probe(Ray& R, GbsSearch& S, const LaunchArgs& A, const Deriv
         S.hi = S.s;
     double sn = S.s - g / dg;
     if (!(sn > S.lo && sn < S.hi)) sn = 0.5 * (S.lo + S.hi);   // also a zero or non-finite slope
-    const double tol = 0.125 * A.event_tol;
+    const double tol = 0.125 * P.event_tol;
     S.flags += 256;
     if (!(fabs(sn - S.s) * S.h <= tol || (S.hi - S.lo) * S.h <= tol || (S.flags >> 8) >= kGbsMaxProbes)) {
         S.s = sn;
@@ -1240,11 +1261,11 @@ __device__ __forceinline__ double pow2_floor(double x)
 // One attempt; returns true when the ray has terminated (outputs written).
 // (S: the extrapolation's event search; unused by the other methods.)
 template <int KIND, int PREC, int METHOD>
-__device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const MetricOps<KIND>& M)
+__device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySettings& P, const MetricOps<KIND>& M)
 {
     bool probe = false;
     if constexpr (METHOD == METHOD_GBS) probe = S.phase != 0;
-    if (!probe && (long long)R.n_acc + R.n_rej >= A.max_steps) {
+    if (!probe && (long long)R.n_acc + R.n_rej >= P.max_steps) {
         ray_fail(R, A);
         return true;
     }
@@ -1260,7 +1281,7 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const Metric
             return true;
         }
     } else {
-        if (PREC == 1 && KIND == 0 && far_field(R, A)) {
+        if (PREC == 1 && KIND == 0 && far_field(R, A, P)) {
             stages32(R, h, y5, k7, e, H5, c5);
             used32 = true;
         } else {
@@ -1274,15 +1295,15 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const Metric
                 stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
             else if constexpr (METHOD == METHOD_GBS)
                 // one call site for attempts and probes (a probe has no error control)
-                stages64_gbs<KIND>(R, M, h, probe ? 0.0 : A.atol, probe ? 0.0 : A.rtol, y5, k7, e, H5, c5);
+                stages64_gbs<KIND>(R, M, h, probe ? 0.0 : P.atol, probe ? 0.0 : P.rtol, y5, k7, e, H5, c5);
             else
                 stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
         }
         if constexpr (METHOD == METHOD_GBS) {
-            if (probe) return gbs_probe(R, S, A, y5, k7, c5);
+            if (probe) return gbs_probe(R, S, A, P, y5, k7, c5);
         }
         R.n_f32 += used32 ? 1 : 0;
-        const double atol = A.atol, rtol = A.rtol;
+        const double atol = P.atol, rtol = P.rtol;
         double acc;
         if constexpr (METHOD == METHOD_GBS) {
             // (the extrapolation applies its own floor in stages64_gbs)
@@ -1334,9 +1355,9 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const Metric
     if (y5.r >= 1.5 * R.rp) R.hgate = fmax(R.hgate, aH);
 
     // ---- events on the accepted step [lam, lam + h]
-    double r_stop = A.horizon_factor * R.rp;
+    double r_stop = P.horizon_factor * R.rp;
     if (KIND == 1 && A.tab_r_min > r_stop) r_stop = A.tab_r_min;
-    const double r_esc = A.r_escape;
+    const double r_esc = P.r_escape;
     const bool hz = (R.r - r_stop > 0.0) && (y5.r - r_stop <= 0.0);
     const bool es = (R.r - r_esc < 0.0) && (y5.r - r_esc >= 0.0);
     const bool dk = R.max_hits > 0 && ((R.cth > 0.0 && c5 <= 0.0) || (R.cth < 0.0 && c5 >= 0.0));
@@ -1368,13 +1389,13 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const Metric
     }
     if (METHOD != METHOD_GBS && dk) {
         if (R.opaque) {
-            if (opaque_hit(R, h, y5, k7, 0.125 * A.event_tol)) {
+            if (opaque_hit(R, h, y5, k7, 0.125 * P.event_tol)) {
                 terminal_step(R, h, y5, k7, 0.0);
                 ray_finish(R, A, CLS_ON_DISK, 8);
                 return true;
             }
         } else {
-            disk_crossing(R, h, y5, k7, 0.125 * A.event_tol);
+            disk_crossing(R, h, y5, k7, 0.125 * P.event_tol);
         }
     }
 
@@ -1481,6 +1502,7 @@ __global__ void __launch_bounds__(256)
     Ray R;
     GbsSearch S;
     S.phase = 0;
+    RaySettings P = launch_settings(A);   // serving: each ray's request's, set with the ray
     bool active = false;
     bool parked = false;       // this lane used its step budget for this launch
     bool exhausted = false;
@@ -1491,6 +1513,7 @@ __global__ void __launch_bounds__(256)
         if (A.slots && A.slot_live[slot]) {
             unpark<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
             A.slot_live[slot] = 0u;
+            P = job_settings(A.jobs[R.job]);
             active = !A.jobs[R.job].cancelled;
             if (!active) done = R.job;
         }
@@ -1542,6 +1565,7 @@ __global__ void __launch_bounds__(256)
                         gid = A.first_ray + id;
                     }
                     active = ray_init<KIND>(R, gid, A, D, M);
+                    if constexpr (SERVE) P = job_settings(A.jobs[R.job]);
                     S.phase = 0;
                     if (!active) done = R.job;
                 }
@@ -1555,7 +1579,7 @@ __global__ void __launch_bounds__(256)
             continue;
         }
         if (active) {
-            active = !ray_step<KIND, PREC, METHOD>(R, S, A, M);
+            active = !ray_step<KIND, PREC, METHOD>(R, S, A, P, M);
             if (!active) {
                 done = R.job;
             } else if (SERVE && A.slots && --budget == 0) {

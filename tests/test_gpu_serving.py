@@ -60,6 +60,37 @@ def test_requests_alone_equal_in_mix(T, precision):
         assert np.all(g["cls"] != 2)
 
 
+def test_requests_with_their_own_tolerance_and_precision(T):
+    """One session serves requests at different tolerances and precisions
+    side by side (an epoch that holds a mixed-precision request runs the mixed
+    instance, whose FP64 path traces the others); each request's outputs equal
+    its trace alone; FP64 requests and mixed ones below rtol 5e-10 take no
+    FP32 stage, the loose mixed ones do."""
+    reqs = stream_requests(6, seed=21)
+    plan = [(1e-8, 0), (1e-8, 1), (3e-10, 0), (1e-9, 1), (3e-11, 1), (1e-7, 1)]
+    outs, tickets = [], []
+    for r, (rtol, prec) in zip(reqs, plan):
+        r["solver"] = dict(r["solver"], rtol=rtol, atol=rtol / 100.0)
+        cam = r["camera"]
+        o = T.alloc_outputs(cam["nx"] * cam["ny"])
+        outs.append(o)
+        tickets.append(T.tartarus_submit(T.make_metric(r["a"]), T.make_camera(cam), T.make_disk(r["disk"]),
+                                         T.make_solver(r["solver"], prec), o))
+    for t in tickets:
+        T.tartarus_wait(t, 120000)
+        assert T.tartarus_poll(t) == 2
+    for r, (rtol, prec), o in zip(reqs, plan, outs):
+        g = T.to_numpy(o)
+        ref = alone(T, r, prec)
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (r["id"], rtol, prec, k)
+        n32 = int(g["n_fp32"].sum())
+        if prec == 0 or rtol < 5e-10:
+            assert n32 == 0, (rtol, prec)
+        elif rtol >= 1e-8:
+            assert n32 > 0, (rtol, prec)
+
+
 def test_arrivals_during_running_work_overlap(T):
     """A request submitted while a large one runs is admitted and finishes before it."""
     big = stream_requests(1, seed=11, res=(384,))[0]
@@ -96,9 +127,10 @@ def test_cancel_and_errors(T):
     T.tartarus_wait(t2, 60000)
     ref = alone(T, r2, 0)
     assert np.array_equal(ref["hit_r"], T.to_numpy(o2)["hit_r"])
-    # a different solver in the same session is refused
+    # another integration method in the same session is refused
+    r3 = dict(r2, solver=dict(r2["solver"], method=1))
     with pytest.raises(T.TartarusError) as e:
-        T.tartarus_submit(*mk(r2, prec=1), o2)
+        T.tartarus_submit(*mk(r3), o2)
     assert e.value.code == T.E_INVALID
     with pytest.raises(T.TartarusError) as e:
         T.tartarus_poll(987654321)
