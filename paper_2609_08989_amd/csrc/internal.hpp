@@ -111,7 +111,7 @@ struct LaunchArgs {
     double turn_r, turn_th;         // turning-point guards (fractions)
     // serving epochs: resume / park ray state (null for one-shot traces)
     double* slots;                  // [nslot][SLOT_DOUBLES] parked state, slot = global lane id
-    long long step_budget;          // attempts per lane per launch before parking (<= 0: none)
+    long long step_budget;          // serving: wavefront iterations per launch, then every lane parks (<= 0: none)
     unsigned int* slot_live;        // [nslot] 1 if a parked ray lives in the slot
     // serving: directory from global ray index to job-table entry, sorted by begin
     const long long* dir_begin;     // null: look up jobs[].ray_begin directly

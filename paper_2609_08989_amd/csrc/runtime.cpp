@@ -600,15 +600,15 @@ extern "C" int tartarus_kernel_time(double* total_ms, long long* launches)
 // Requests are admitted in arrival order while their output bytes plus the
 // ray-slot arena fit the HBM budget (and a request-table entry is free).  All
 // admitted requests share one device queue of global ray indices; the
-// persistent kernel runs in epochs of a bounded number of attempts per lane,
-// parks unfinished rays in their lane's slot (exact bits) and resumes them in
+// persistent kernel runs in epochs of a bounded number of wavefront
+// iterations, parks unfinished rays in their lane's slot (exact bits) and resumes them in
 // the next epoch, so requests that arrive while others are on the device join
 // at the next epoch boundary and their rays overlap with the running ones.
 // ---------------------------------------------------------------------------
 namespace {
 
 constexpr int kMaxEntries = 256;        // request-table entries (requests in flight)
-constexpr long long kEpochAttempts = 192;  // attempts per lane per epoch
+constexpr long long kEpochIterations = 192;  // wavefront iterations (attempts) per epoch
 
 int64_t now_ns()
 {
@@ -935,7 +935,7 @@ int server_round(std::unique_lock<std::mutex>& lk)
     A.head = S.dhead;
     A.slots = S.slots;
     A.slot_live = S.slot_live;
-    A.step_budget = kEpochAttempts;
+    A.step_budget = kEpochIterations;
     if (const char* e = std::getenv("TARTARUS_EPOCH_ATTEMPTS")) {   // experiment override
         const long long v = std::atoll(e);
         if (v > 0) A.step_budget = v;

@@ -1504,10 +1504,10 @@ __global__ void __launch_bounds__(256)
     S.phase = 0;
     RaySettings P = launch_settings(A);   // serving: each ray's request's, set with the ray
     bool active = false;
-    bool parked = false;       // this lane used its step budget for this launch
+    bool parked = false;       // serving: this launch's epoch has ended for the lane
     bool exhausted = false;
     int done = -1;             // serving: job of a ray that ended this iteration
-    long long budget = A.step_budget;
+    long long iter = 0;        // serving: wavefront iterations with work this launch
     const long long slot = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if constexpr (SERVE) {
         if (A.slots && A.slot_live[slot]) {
@@ -1580,16 +1580,21 @@ __global__ void __launch_bounds__(256)
         }
         if (active) {
             active = !ray_step<KIND, PREC, METHOD>(R, S, A, P, M);
-            if (!active) {
-                done = R.job;
-            } else if (SERVE && A.slots && --budget == 0) {
-                park<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
-                A.slot_live[slot] = 1u;
-                active = false;
-                parked = true;
-            }
+            if (!active) done = R.job;
         }
         if constexpr (SERVE) {
+            // An epoch is step_budget iterations of the wavefront: then every
+            // lane parks its ray at once.  (A per-lane attempt budget let
+            // lanes that had waited for a refill run on alone at the end of
+            // the epoch, with the rest of the wavefront idle.)
+            if (A.slots && A.step_budget > 0 && ++iter >= A.step_budget) {
+                if (active) {
+                    park<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
+                    A.slot_live[slot] = 1u;
+                    active = false;
+                }
+                parked = true;
+            }
             if (A.remaining) count_done(A, done);
         }
     }
