@@ -1094,10 +1094,13 @@ __device__ __forceinline__ double ipow(double y)
 // x^(-1/P) on the range step_factor passes in: an FP32 estimate refined by
 // two Newton steps on y^-P = x (y <- y ((P + 1) - x y^P) / P), which take the
 // ~1e-7 relative error of the estimate below an ulp of the double result.
+// The estimate uses the hardware log2 and exp2 directly: x, its logarithm
+// scaled by -1/P and the result are normal floats there (x in [1e-24, 1e16]),
+// where the library functions' denormal handling returns the same values.
 template <int P>
 __device__ __forceinline__ double pow_m_inv(double x)
 {
-    double y = (double)exp2f(log2f((float)x) * (-1.0f / (float)P));
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)x) * (-1.0f / (float)P));
 #pragma unroll
     for (int i = 0; i < 2; ++i) y = y * fma(-x, ipow<P>(y), (double)(P + 1)) * (1.0 / (double)P);
     return y;
