@@ -50,9 +50,11 @@ TT_HD inline double flip_sign(double x, unsigned hi_bit)
     return x;
 }
 
-// sincos64 with the coefficients taken from coef(i) (i indexes kSinCos64).
+// The reduced argument's sine and cosine (sr, cr) and the quadrant q: with
+// odd q the two swap, and sin x = +-(q odd ? cr : sr) with the sign of bit 1 of
+// q, cos x = +-(q odd ? sr : cr) with the sign of bit 1 of q + 1.
 template <class Coef>
-TT_HD inline void sincos64_with(double x, double* sp, double* cp, Coef coef)
+TT_HD inline void sincos64_parts(double x, double* srp, double* crp, int* qp, Coef coef)
 {
     const double k = std::rint(x * coef(0));
     double r = std::fma(-k, coef(1), x);
@@ -69,11 +71,21 @@ TT_HD inline void sincos64_with(double x, double* sp, double* cp, Coef coef)
 #pragma unroll
     for (int i = 11; i <= 15; ++i) pc = std::fma(pc, r2, coef(i));
     pc = std::fma(pc, r2, -0.5);
-    const double cr = std::fma(pc, r2, 1.0);
+    *crp = std::fma(pc, r2, 1.0);
+    *srp = sr;
     // quadrant: |k| < 2^20, so the int conversion is exact (one instruction,
-    // where a 64-bit integer conversion of a double takes four); the signs are
-    // applied by flipping the sign bit (same bits as negation)
-    const int q = ((int)k) & 3;
+    // where a 64-bit integer conversion of a double takes four)
+    *qp = ((int)k) & 3;
+}
+
+// sincos64 with the coefficients taken from coef(i) (i indexes kSinCos64).
+// The signs are applied by flipping the sign bit (same bits as negation).
+template <class Coef>
+TT_HD inline void sincos64_with(double x, double* sp, double* cp, Coef coef)
+{
+    double sr, cr;
+    int q;
+    sincos64_parts(x, &sr, &cr, &q, coef);
     const double s = (q & 1) ? cr : sr;
     const double c = (q & 1) ? sr : cr;
     *sp = flip_sign(s, (unsigned)(q & 2) << 30);

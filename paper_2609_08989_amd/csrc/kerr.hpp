@@ -29,12 +29,18 @@ template <class Coef = SinCosImm>
 __device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double pr, double pth, double pt,
                                            double pph, Deriv<double>& d, double& H, double& cth, Coef coef = {})
 {
-    double s, c;
-    sincos64_with(th, &s, &c, coef);
+    // sin and cos from the reduced argument's (sr, cr) and the quadrant q: the
+    // squares need only the swap of odd quadrants, sin cos is negative exactly
+    // for odd q, and the signed cosine is formed only where cth is used
+    double sr, cr;
+    int q;
+    sincos64_parts(th, &sr, &cr, &q, coef);
+    const bool odd = (q & 1) != 0;
+    const double sr2 = sr * sr, cr2 = cr * cr;
     const double a2 = a * a;
     const double r2 = r * r;
-    const double s2 = s * s;
-    const double sig = fma(a2, c * c, r2);
+    const double s2 = odd ? cr2 : sr2;
+    const double sig = fma(a2, odd ? sr2 : cr2, r2);
     const double del = fma(r, r - 2.0, a2);
     // 1/Sigma, 1/Delta and 1/sin^2 from one reciprocal of their product (radii
     // are bounded by the escape radius, so the product stays in range)
@@ -60,10 +66,11 @@ __device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double
     d.pr = iS * fma(r, fma(2.0 * pt, PiD, iSK), (1.0 - r) * fma(pr, pr, PiD * PiD));
     // dp_theta = -(1/2) d(K / Sigma)/dtheta with dK/dtheta = 2 sin cos (a^2 p_t^2 - (p_phi / sin^2)^2)
     // and dSigma/dtheta = -2 a^2 sin cos
-    const double q = pph * is2;
-    d.pth = -(iS * (s * c)) * fma(a2, fma(pt, pt, iSK), -(q * q));
+    const double qp = pph * is2;
+    const double sc = flip_sign(sr * cr, (unsigned)(q & 1) << 31);
+    d.pth = -(iS * sc) * fma(a2, fma(pt, pt, iSK), -(qp * qp));
     H = 0.5 * iSK;
-    cth = c;
+    cth = flip_sign(odd ? sr : cr, (unsigned)((q + 1) & 2) << 30);
 }
 
 // Covariant components (g_tt, g_tphi, g_rr, g_thth, g_phph) of Kerr at (r, theta).
