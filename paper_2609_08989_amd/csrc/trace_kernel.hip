@@ -1526,6 +1526,27 @@ __global__ void __launch_bounds__(256)
     long long next = 0, end = 0;
     const long long n_rays = A.total_rays - A.first_ray;
     for (;;) {
+        if (__any(active)) {
+            if (active) {
+                active = !ray_step<KIND, PREC, METHOD>(R, S, A, P, M);
+                if (!active) done = R.job;
+            }
+            if constexpr (SERVE) {
+                // An epoch is step_budget iterations of the wavefront: then every
+                // lane parks its ray at once.  (A per-lane attempt budget let
+                // lanes that had waited for a refill run on alone at the end of
+                // the epoch, with the rest of the wavefront idle.)
+                if (A.slots && A.step_budget > 0 && ++iter >= A.step_budget) {
+                    if (active) {
+                        park<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
+                        A.slot_live[slot] = 1u;
+                        active = false;
+                    }
+                    parked = true;
+                }
+                if (A.remaining) count_done(A, done);
+            }
+        }
         if (!exhausted) {
             const unsigned long long need = __ballot(!active && !parked);
             const int nneed = __popcll(need);
@@ -1579,27 +1600,8 @@ __global__ void __launch_bounds__(256)
         }
         if (!__any(active)) {
             if (exhausted || !__any(!parked)) break;
-            continue;
         }
-        if (active) {
-            active = !ray_step<KIND, PREC, METHOD>(R, S, A, P, M);
-            if (!active) done = R.job;
-        }
-        if constexpr (SERVE) {
-            // An epoch is step_budget iterations of the wavefront: then every
-            // lane parks its ray at once.  (A per-lane attempt budget let
-            // lanes that had waited for a refill run on alone at the end of
-            // the epoch, with the rest of the wavefront idle.)
-            if (A.slots && A.step_budget > 0 && ++iter >= A.step_budget) {
-                if (active) {
-                    park<METHOD>(R, S, A.slots + slot * SLOT_DOUBLES);
-                    A.slot_live[slot] = 1u;
-                    active = false;
-                }
-                parked = true;
-            }
-            if (A.remaining) count_done(A, done);
-        }
+
     }
 }
 
