@@ -65,3 +65,13 @@ def test_gate_tolerances_are_the_listed_ones():
     assert max(b.GATE_RTOLS_BEYOND) < min(b.GATE_RTOLS)
     s = b.solver_at({"solver": {"rtol": 1e-8, "atol": 1e-10, "r_escape": 1100.0}}, 3e-10)
     assert s["rtol"] == 3e-10 and s["atol"] == 3e-12
+
+
+def test_gather_roofline_counts_six_rhs_per_attempt_and_one_per_ray():
+    rec = {"attempts_per_ray": 10.0, "kernel_ms": 2.0}
+    g = bench.gather_roofline(rec, 1000)
+    rhs = 10.0 * 1000 * 6 + 1000
+    assert g["rhs_per_launch"] == rhs
+    assert abs(g["achieved"] - rhs * 640 / 2e-3 / 1e12) < 1e-12
+    assert abs(g["frac"] - g["achieved"] / g["peak"]) < 1e-15
+    assert abs(g["peak"] - 8 * 16 * 128 * 2.4e9 / 1e12) < 1e-9

@@ -118,6 +118,13 @@ static void filling()
     CHECK(J.ray_begin == 384 && J.ray_count == 192 && J.nx == 16 && J.ny == 12);
     CHECK(J.cls == i32.data() + 192 && J.final_rtp == f64.data() + 576 && J.hit_order == i32.data() + 576);
     CHECK(J.disk_flags == (DISK_OPAQUE | DISK_INTRINSIC) && J.max_hits == 2 && J.event_tol == 1e-12);
+    // the request's own solver settings, and FP32 stages only for mixed
+    // precision at a tolerance where they can pass the rounding test
+    CHECK(J.rtol == s.rtol && J.atol == s.atol && J.h0_frac == s.h0_frac && J.max_steps == s.max_steps);
+    CHECK(J.horizon_factor == s.horizon_factor && J.r_escape == s.r_escape && J.allow32 == 0);
+    { tartarus_solver b = s; b.precision = 1; fill_job(J, &m, c, &d, &b, &o, 0, 0, nullptr); CHECK(J.allow32 == 1); }
+    { tartarus_solver b = s; b.precision = 1; b.rtol = 1e-10; fill_job(J, &m, c, &d, &b, &o, 0, 0, nullptr);
+      CHECK(J.allow32 == 0 && kernel_precision(&b) == TARTARUS_PREC_FP64); }
     LaunchArgs A;
     fill_args(A, &m, &s);
     CHECK(A.rtol == 1e-8 && A.table == nullptr && A.r_switch_factor == kDefaultSwitch && A.slots == nullptr);
