@@ -68,8 +68,9 @@ def test_gate_tolerances_are_the_listed_ones():
 
 
 def test_gather_roofline_counts_six_rhs_per_attempt_and_one_per_ray():
+    b = load_bench()
     rec = {"attempts_per_ray": 10.0, "kernel_ms": 2.0}
-    g = bench.gather_roofline(rec, 1000)
+    g = b.gather_roofline(rec, 1000)
     rhs = 10.0 * 1000 * 6 + 1000
     assert g["rhs_per_launch"] == rhs
     assert abs(g["achieved"] - rhs * 640 / 2e-3 / 1e12) < 1e-12
