@@ -67,7 +67,8 @@ __device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double
     // dp_theta = -(1/2) d(K / Sigma)/dtheta with dK/dtheta = 2 sin cos (a^2 p_t^2 - (p_phi / sin^2)^2)
     // and dSigma/dtheta = -2 a^2 sin cos
     const double qp = pph * is2;
-    const double sc = flip_sign(sr * cr, (unsigned)(q & 1) << 31);
+    const double scr = sr * cr;
+    const double sc = odd ? -scr : scr;
     d.pth = -(iS * sc) * fma(a2, fma(pt, pt, iSK), -(qp * qp));
     H = 0.5 * iSK;
     cth = flip_sign(odd ? sr : cr, (unsigned)((q + 1) & 2) << 30);
