@@ -919,25 +919,27 @@ __device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>
         const int n = 2 * (i + 1);
         const double hs = h / (double)n;
         const double h2 = 2.0 * hs;
-        // d_0 = 0, d_1 = hs f(y)
-        double pt_ = 0.0, pr_ = 0.0, pth_ = 0.0, pph_ = 0.0, ppr_ = 0.0, ppth_ = 0.0;
-        double dt = hs * R.k.t, dr = hs * R.k.r, dth = hs * R.k.th;
-        double dph = hs * R.k.ph, dpr = hs * R.k.pr, dpth = hs * R.k.pth;
+        // d_0 = 0 (in e_), d_1 = hs f(y) (in o_); d_{m+1} = d_{m-1} + 2 hs f(y + d_m).
+        // n is even, so the substeps go in pairs: each pair updates the even
+        // then the odd sequence in place, and no value changes registers.
+        double et = 0.0, er = 0.0, eth = 0.0, eph = 0.0, epr = 0.0, epth = 0.0;
+        double ot = hs * R.k.t, orr = hs * R.k.r, oth = hs * R.k.th;
+        double oph = hs * R.k.ph, opr = hs * R.k.pr, opth = hs * R.k.pth;
         Deriv<double> dz;
-        for (int m = 1;; ++m) {
+        for (int m = 1;; m += 2) {
             double Hd, cd;
-            M.rhs(a, R.r + dr, R.th + dth, R.pr + dpr, R.pth + dpth, R.pt, R.pph, dz, Hd, cd);
-            if (m == n) break;
-            // d_{m+1} = d_{m-1} + 2 hs f(y + d_m)
-            const double nt = fma(h2, dz.t, pt_), nr = fma(h2, dz.r, pr_), nth = fma(h2, dz.th, pth_);
-            const double nph = fma(h2, dz.ph, pph_), npr = fma(h2, dz.pr, ppr_), npth = fma(h2, dz.pth, ppth_);
-            pt_ = dt; pr_ = dr; pth_ = dth; pph_ = dph; ppr_ = dpr; ppth_ = dpth;
-            dt = nt; dr = nr; dth = nth; dph = nph; dpr = npr; dpth = npth;
+            M.rhs(a, R.r + orr, R.th + oth, R.pr + opr, R.pth + opth, R.pt, R.pph, dz, Hd, cd);
+            et = fma(h2, dz.t, et); er = fma(h2, dz.r, er); eth = fma(h2, dz.th, eth);
+            eph = fma(h2, dz.ph, eph); epr = fma(h2, dz.pr, epr); epth = fma(h2, dz.pth, epth);
+            M.rhs(a, R.r + er, R.th + eth, R.pr + epr, R.pth + epth, R.pt, R.pph, dz, Hd, cd);
+            if (m + 1 == n) break;
+            ot = fma(h2, dz.t, ot); orr = fma(h2, dz.r, orr); oth = fma(h2, dz.th, oth);
+            oph = fma(h2, dz.ph, oph); opr = fma(h2, dz.pr, opr); opth = fma(h2, dz.pth, opth);
         }
-        // smoothing: (d_n + d_{n-1} + hs f(y + d_n)) / 2
-        double vt = 0.5 * (pt_ + fma(hs, dz.t, dt)), vr = 0.5 * (pr_ + fma(hs, dz.r, dr));
-        double vth = 0.5 * (pth_ + fma(hs, dz.th, dth)), vph = 0.5 * (pph_ + fma(hs, dz.ph, dph));
-        double vpr = 0.5 * (ppr_ + fma(hs, dz.pr, dpr)), vpth = 0.5 * (ppth_ + fma(hs, dz.pth, dpth));
+        // smoothing: (d_n + d_{n-1} + hs f(y + d_n)) / 2, with d_n in e_ and d_{n-1} in o_
+        double vt = 0.5 * (ot + fma(hs, dz.t, et)), vr = 0.5 * (orr + fma(hs, dz.r, er));
+        double vth = 0.5 * (oth + fma(hs, dz.th, eth)), vph = 0.5 * (oph + fma(hs, dz.ph, eph));
+        double vpr = 0.5 * (opr + fma(hs, dz.pr, epr)), vpth = 0.5 * (opth + fma(hs, dz.pth, epth));
         bt = fmax(bt, fabs(vt)); br = fmax(br, fabs(vr)); bth = fmax(bth, fabs(vth));
         bph = fmax(bph, fabs(vph)); bpr = fmax(bpr, fabs(vpr)); bpth = fmax(bpth, fabs(vpth));
         // fold into the tableau
