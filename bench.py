@@ -11,8 +11,8 @@ device, so the timed region reads nothing from the host.
 
 The metric is rays/s at |H| <= 1e-8: before anything is timed, the image is
 traced (untimed) at rtol in {1e-8, 3e-9, 1e-9, 3e-10, 1e-10} (atol = rtol /
-100), and at 3e-11 and 1e-11 if none of those passes, in FP64 and in mixed
-precision, and the constraint gate (max |H| over accepted states with
+100), and further along 7e-11, 5e-11, 3e-11, 2e-11, 1e-11 (the 1-2-3-5-7
+steps of a decade) if none of those passes, in FP64 and in mixed precision, and the constraint gate (max |H| over accepted states with
 r >= 1.5 r_+, every non-failed ray) is read off the outputs.  The headline value is FP64 at the loosest tolerance whose gate
 holds; mixed precision is timed at that same tolerance and at its own loosest
 passing tolerance (or reported with its gate fraction where none passes).
@@ -44,7 +44,7 @@ METRIC = "rays/sec at |H|≤1e-8 (FP64 vs mixed, same GPU); p50/p99 image latenc
 HEADLINE = "kerr0998_2048"
 HEADLINE_NAME = "kerr_a0.998_i17deg_r1000_2048x2048_disk_isco_to_30M"
 GATE_RTOLS = (1e-8, 3e-9, 1e-9, 3e-10, 1e-10)
-GATE_RTOLS_BEYOND = (3e-11, 1e-11)   # searched only when no listed tolerance passes
+GATE_RTOLS_BEYOND = (7e-11, 5e-11, 3e-11, 2e-11, 1e-11)   # searched only when no listed tolerance passes
 GATE_H = 1e-8
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 GATHER_BYTES_PER_RHS = 640
@@ -244,7 +244,8 @@ def gather_roofline(rec: dict, n_rays: int) -> dict:
 def gate_search(T, S, prec):
     """Untimed traces at each listed tolerance: the gate per tolerance and the
     loosest tolerance whose gate holds; when none of the listed ones does, the
-    search goes on at 3e-11 and 1e-11 (None if no tolerance passes)."""
+    search goes on down the 1-2-3-5-7 steps from 7e-11 to 1e-11 (None if no
+    tolerance passes)."""
     table, first = {}, None
     for rtol in GATE_RTOLS + GATE_RTOLS_BEYOND:
         if rtol in GATE_RTOLS_BEYOND and first is not None:
