@@ -21,9 +21,14 @@ ARCH = "gfx950"
 # materialised in a VGPR pair; hoisting them all out of the persistent loop
 # costs ~60 VGPRs and forces scratch spills.  Rematerialising them at the use
 # keeps the integrator spill-free.
+# -fmacf64-inst: without the two-address v_fmac_f64 the compiler emits the
+# three-address v_fma_f64, which takes a scalar-register addend directly; with
+# it, every fused multiply-add whose addend is a coefficient in scalar
+# registers first copied that coefficient into a VGPR pair (two moves).
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
     "-mllvm", "-disable-machine-licm",
     "-I", os.path.join(ROOT, "include"),
 ]

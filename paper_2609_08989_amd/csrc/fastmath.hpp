@@ -39,6 +39,18 @@ struct SinCosImm {
     TT_HD double operator()(int i) const { return kSinCos64[i]; }
 };
 
+// Coefficients of the angle shift sin, cos(theta0 + d) from those of theta0
+// for |d| <= 1/16: sin d = d + d^3 (s1 + z (s2 + z s3)) and cos d - 1 =
+// z (-1/2 + z (c2 + z (c3 + z c4))), z = d^2, the Taylor series economized on
+// that interval (truncation below 5e-18 relative and 5e-22; sincos_coeffs.py
+// derives them).  Order: s3, s2, s1, c4, c3, c2.
+constexpr double kShift64[6] = {-0.00019839117033214164, 0.0083333332807754186, -0.16666666666662561,
+                                2.4798896288531483e-05,  -0.00138888887969124,   0.041666666666653834};
+
+struct ShiftImm {
+    TT_HD double operator()(int i) const { return kShift64[i]; }
+};
+
 // x with its sign bit XORed with bit 31 of hi_bit (the other bits of hi_bit
 // must be zero).
 TT_HD inline double flip_sign(double x, unsigned hi_bit)
@@ -76,6 +88,33 @@ TT_HD inline void sincos64_parts(double x, double* srp, double* crp, int* qp, Co
     // quadrant: |k| < 2^20, so the int conversion is exact (one instruction,
     // where a 64-bit integer conversion of a double takes four)
     *qp = ((int)k) & 3;
+}
+
+// x y + z rounded twice (never fused): the shift polynomials' first steps,
+// whose two coefficients, as operands of one fused instruction, would be more
+// scalar registers than one instruction may read and cost a copy.
+TT_HD inline double mul_then_add(double x, double y, double z)
+{
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+    return x * y + z;
+}
+
+// sin and cos of theta0 + dt from s0 = sin(theta0), c0 = cos(theta0), for
+// |dt| <= 1/16: the shift polynomials (kShift64 taken from coef(i)), then the
+// angle-sum identities with the small terms added last (about one ulp each).
+// The sine keeps its relative accuracy while |dt| stays well below |s0|; the
+// caller checks both bounds.
+template <class Coef>
+TT_HD inline void sincos_shift(double s0, double c0, double dt, double& s, double& c, Coef coef)
+{
+    const double z = dt * dt;
+    const double ps = std::fma(mul_then_add(z, coef(0), coef(1)), z, coef(2));
+    const double sd = std::fma(dt * z, ps, dt);   // sin(dt)
+    const double cm = z * std::fma(std::fma(mul_then_add(z, coef(3), coef(4)), z, coef(5)), z, -0.5);   // cos(dt) - 1
+    s = std::fma(s0, cm, std::fma(c0, sd, s0));
+    c = std::fma(c0, cm, std::fma(-s0, sd, c0));
 }
 
 // sincos64 with the coefficients taken from coef(i) (i indexes kSinCos64).

@@ -133,7 +133,7 @@ struct LaunchArgs {
     int pad3;
 };
 
-constexpr int SLOT_DOUBLES = 40;   // a parked ray (31 doubles) and its event search (8)
+constexpr int SLOT_DOUBLES = 40;   // a parked ray (32 doubles) and its event search (8)
 
 constexpr long long align256(long long b) { return (b + 255) / 256 * 256; }
 

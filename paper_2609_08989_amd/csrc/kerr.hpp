@@ -23,24 +23,14 @@ struct Deriv {
     T t, r, th, ph, pr, pth;
 };
 
-// FP64 right-hand side.  Also returns H (Eq. (1)) and cos(theta) of the point.
-// coef supplies the sincos64 coefficients (compile-time immediates by default).
-template <class Coef = SinCosImm>
-__device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double pr, double pth, double pt,
-                                           double pph, Deriv<double>& d, double& H, double& cth, Coef coef = {})
+// FP64 right-hand side from sin^2(theta) s2, cos^2(theta) c2 and
+// sin(theta) cos(theta) sc; also returns H (Eq. (1)).
+__device__ __forceinline__ void kerr_rhs64_trig(double a, double r, double s2, double c2, double sc, double pr,
+                                                double pth, double pt, double pph, Deriv<double>& d, double& H)
 {
-    // sin and cos from the reduced argument's (sr, cr) and the quadrant q: the
-    // squares need only the swap of odd quadrants, sin cos is negative exactly
-    // for odd q, and the signed cosine is formed only where cth is used
-    double sr, cr;
-    int q;
-    sincos64_parts(th, &sr, &cr, &q, coef);
-    const bool odd = (q & 1) != 0;
-    const double sr2 = sr * sr, cr2 = cr * cr;
     const double a2 = a * a;
     const double r2 = r * r;
-    const double s2 = odd ? cr2 : sr2;
-    const double sig = fma(a2, odd ? sr2 : cr2, r2);
+    const double sig = fma(a2, c2, r2);
     const double del = fma(r, r - 2.0, a2);
     // 1/Sigma, 1/Delta and 1/sin^2 from one reciprocal of their product (radii
     // are bounded by the escape radius, so the product stays in range)
@@ -67,11 +57,30 @@ __device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double
     // dp_theta = -(1/2) d(K / Sigma)/dtheta with dK/dtheta = 2 sin cos (a^2 p_t^2 - (p_phi / sin^2)^2)
     // and dSigma/dtheta = -2 a^2 sin cos
     const double qp = pph * is2;
-    const double scr = sr * cr;
-    const double sc = odd ? -scr : scr;
     d.pth = -(iS * sc) * fma(a2, fma(pt, pt, iSK), -(qp * qp));
     H = 0.5 * iSK;
+}
+
+// FP64 right-hand side at polar angle th.  Also returns H (Eq. (1)), cos(theta)
+// and sin(theta) of the point.  coef supplies the sincos64 coefficients
+// (compile-time immediates by default).
+template <class Coef = SinCosImm>
+__device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double pr, double pth, double pt,
+                                           double pph, Deriv<double>& d, double& H, double& cth, double& sth,
+                                           Coef coef = {})
+{
+    // sin and cos from the reduced argument's (sr, cr) and the quadrant q: the
+    // squares need only the swap of odd quadrants, sin cos is negative exactly
+    // for odd q, and the signed values are formed only where they are used
+    double sr, cr;
+    int q;
+    sincos64_parts(th, &sr, &cr, &q, coef);
+    const bool odd = (q & 1) != 0;
+    const double sr2 = sr * sr, cr2 = cr * cr;
+    const double scr = sr * cr;
+    kerr_rhs64_trig(a, r, odd ? cr2 : sr2, odd ? sr2 : cr2, odd ? -scr : scr, pr, pth, pt, pph, d, H);
     cth = flip_sign(odd ? sr : cr, (unsigned)((q + 1) & 2) << 30);
+    sth = flip_sign(odd ? cr : sr, (unsigned)(q & 2) << 30);
 }
 
 // Covariant components (g_tt, g_tphi, g_rr, g_thth, g_phph) of Kerr at (r, theta).

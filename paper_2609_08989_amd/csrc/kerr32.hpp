@@ -57,7 +57,7 @@ __device__ __forceinline__ void kerr_rhs32(float a, float r, float th, float pr,
 // FP64 Hamiltonian (Eq. (1), separated form) and cos(theta) at a point, for the
 // constraint monitor of steps whose stages ran in FP32.
 __device__ __forceinline__ double kerr_H64(double a, double r, double th, double pr, double pth, double pt,
-                                           double pph, double& cth)
+                                           double pph, double& cth, double& sth)
 {
     double s, c;
     sincos64(th, &s, &c);
@@ -68,6 +68,7 @@ __device__ __forceinline__ double kerr_H64(double a, double r, double th, double
     const double W = fma(a * s2, pt, pph);
     const double K = fma(del * pr, pr, fma(pth, pth, W * W * rcp64(s2) - P * P * rcp64(del)));
     cth = c;
+    sth = s;
     return 0.5 * K * rcp64(sig);
 }
 

@@ -1,4 +1,5 @@
-"""Derives the polynomial coefficients of sincos64 (fastmath.hpp).
+"""Derives the polynomial coefficients of sincos64 (fastmath.hpp) and of the
+angle shift from a step's start (kShift64).
 
 sin(r)/r and cos(r) are series in z = r^2.  On |r| <= pi/4 (z <= 0.61686) the
 Taylor series are truncated far beyond double precision, re-expanded in
@@ -54,9 +55,15 @@ def economize(c, deg, zmax=ZMAX):
     return mz, bound
 
 
+# The angle shift (sincos_shift in kerr.hpp) evaluates sin(d)/d and cos(d) on
+# |d| <= 1/16 (z <= 1/256), degrees 3 and 4 in z; their z^0 and z^1
+# coefficients round to 1 and -1/2 exactly, and the code takes them so.
+ZMAX_SHIFT = F(1, 256)
+
 if __name__ == "__main__":
-    for name, odd, deg in (("sin(r)/r", True, 6), ("cos(r)", False, 7)):
-        mz, bound = economize(taylor(odd, 14), deg)
+    for name, odd, deg, zmax in (("sin(r)/r", True, 6, ZMAX), ("cos(r)", False, 7, ZMAX),
+                                 ("sin(d)/d (shift)", True, 3, ZMAX_SHIFT), ("cos(d) (shift)", False, 4, ZMAX_SHIFT)):
+        mz, bound = economize(taylor(odd, 14), deg, zmax)
         print(f"{name}: degree {deg} in z, truncation bound {float(bound):.2e}")
         for k, v in enumerate(mz):
             print(f"  z^{k}: {float(v):.17g}")

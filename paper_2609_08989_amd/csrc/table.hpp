@@ -134,7 +134,8 @@ __device__ __forceinline__ void table_metric(const TableView& T, double r, doubl
 // dx^mu = g^{mu nu} p_nu and dp_mu = 1/2 (d_mu g_ab) dx^a dx^b (the same as
 // -1/2 (d_mu g^{ab}) p_a p_b, since d g^{-1} = -g^{-1} (d g) g^{-1}).
 __device__ __forceinline__ void table_rhs64(const TableView& T, double r, double th, double pr, double pth,
-                                            double pt, double pph, Deriv<double>& d, double& H, double& cth)
+                                            double pt, double pph, Deriv<double>& d, double& H, double& cth,
+                                            double& sth)
 {
     double g[5], gr[5], gt[5];
     table_metric<true, true>(T, r, th, g, gr, gt);
@@ -150,8 +151,7 @@ __device__ __forceinline__ void table_rhs64(const TableView& T, double r, double
     d.pth = 0.5 * (gt[0] * d.t * d.t + 2.0 * gt[1] * d.t * d.ph + gt[2] * d.r * d.r + gt[3] * d.th * d.th +
                    gt[4] * d.ph * d.ph);
     H = 0.5 * (d.t * pt + d.ph * pph + d.r * pr + d.th * pth);
-    double sn;
-    sincos64(th, &sn, &cth);
+    sincos64(th, &sth, &cth);
 }
 
 }  // namespace tartarus

@@ -125,7 +125,7 @@ enum { CLS_ESCAPED = 0, CLS_CAPTURED = 1, CLS_FAILED = 2, CLS_ON_DISK = 3 };
 struct Ray {
     double t, r, th, ph, pr, pth, pt, pph;
     Deriv<double> k;   // right-hand side at the current state (first same as last)
-    double cth;        // cos(theta) at the current state
+    double cth, sth;   // cos(theta) and sin(theta) at the current state
     double lam, h;
     double hmax, hgate;
     double a, rp;      // spin and horizon radius r_+
@@ -163,14 +163,44 @@ struct MetricOps {
     TableView T;
     // coef: where the analytic right-hand side takes its sine/cosine
     // coefficients from (immediates unless a stage loop passes SinCosLoad)
+    // Right-hand side at (r, th, pr, pth); also H, cos(th) and sin(th).
+    template <class Coef = SinCosImm>
+    __device__ __forceinline__ void rhs_sc(double a, double r, double th, double pr, double pth, double pt, double pph,
+                                           Deriv<double>& d, double& H, double& c, double& s, Coef coef = {}) const
+    {
+        if (KIND == 0)
+            kerr_rhs64(a, r, th, pr, pth, pt, pph, d, H, c, s, coef);
+        else
+            table_rhs64(T, r, th, pr, pth, pt, pph, d, H, c, s);
+    }
     template <class Coef = SinCosImm>
     __device__ __forceinline__ void rhs(double a, double r, double th, double pr, double pth, double pt, double pph,
                                         Deriv<double>& d, double& H, double& c, Coef coef = {}) const
     {
-        if (KIND == 0)
-            kerr_rhs64(a, r, th, pr, pth, pt, pph, d, H, c, coef);
-        else
-            table_rhs64(T, r, th, pr, pth, pt, pph, d, H, c);
+        double s;
+        rhs_sc(a, r, th, pr, pth, pt, pph, d, H, c, s, coef);
+    }
+    // The same at a stage point near the step's start (th0, with sine s0 and
+    // cosine c0): where |th - th0| <= dmax the analytic metric takes sin and
+    // cos of th from those of th0 by the angle-sum identities, elsewhere from
+    // th itself.  Returns cos(th) in c.
+    template <class Coef, class Shift>
+    __device__ __forceinline__ void rhs_near(double a, double r, double th, double th0, double s0, double c0,
+                                             double dmax, double pr, double pth, double pt, double pph,
+                                             Deriv<double>& d, double& H, double& c, Coef coef, Shift shift) const
+    {
+        if constexpr (KIND == 0) {
+            const double dt = th - th0;
+            double sn, cs;
+            if (fabs(dt) <= dmax)
+                sincos_shift(s0, c0, dt, sn, cs, shift);
+            else
+                sincos64_with(th, &sn, &cs, coef);
+            kerr_rhs64_trig(a, r, sn * sn, cs * cs, sn * cs, pr, pth, pt, pph, d, H);
+            c = cs;
+        } else {
+            rhs(a, r, th, pr, pth, pt, pph, d, H, c);
+        }
     }
     __device__ __forceinline__ void metric(double a, double r, double th, double g[5]) const
     {
@@ -416,7 +446,7 @@ __device__ bool ray_init(Ray& R, long long gid, const LaunchArgs& A, const JobDi
     R.guard_th = (float)(A.turn_th * sqrt(fmax(Q, 1e-12)));
     R.guard_r = (float)(A.turn_r * fabs(R.pt));
     double H;
-    M.rhs(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, H, R.cth);
+    M.rhs_sc(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, H, R.cth, R.sth);
     R.hmax = fabs(H);
     R.hgate = R.r >= 1.5 * R.rp ? fabs(H) : 0.0;
     R.lam = 0.0;
@@ -600,7 +630,7 @@ __device__ __forceinline__ bool far_field(const Ray& R, const LaunchArgs& A, con
 // norm; H(y5) and cos(theta5) are evaluated in FP64 for the constraint monitor
 // and the event tests.
 __device__ __forceinline__ void stages32(const Ray& R, double h, Deriv<double>& y5, Deriv<double>& k7d,
-                                         Deriv<double>& e, double& H5, double& c5)
+                                         Deriv<double>& e, double& H5, double& c5, double& s5)
 {
     const float a = (float)R.a, hf = (float)h;
     const float r0 = (float)R.r, th0 = (float)R.th, pr0 = (float)R.pr, pth0 = (float)R.pth;
@@ -649,7 +679,7 @@ __device__ __forceinline__ void stages32(const Ray& R, double h, Deriv<double>& 
     k7d.ph = (double)k7.ph;
     k7d.pr = (double)k7.pr;
     k7d.pth = (double)k7.pth;
-    H5 = kerr_H64(R.a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, c5);
+    H5 = kerr_H64(R.a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, c5, s5);
 #undef TT_S3
 #undef TT_S4
 #undef TT_S5
@@ -704,6 +734,13 @@ struct SinCosLoad {
     __device__ double operator()(int i) const { return p[i]; }
 };
 
+// The angle-shift coefficients, loaded the same way once per attempt.
+__constant__ double kShift64Const[6] = {kShift64[0], kShift64[1], kShift64[2], kShift64[3], kShift64[4], kShift64[5]};
+struct ShiftLoad {
+    ConstDouble* p;
+    __device__ double operator()(int i) const { return p[i]; }
+};
+
 // The analytic metric's stages load the sine/cosine coefficients; the
 // tabulated metric does not evaluate them in its right-hand side.
 template <int KIND>
@@ -716,43 +753,50 @@ __device__ __forceinline__ auto sincos_source()
 }
 template <int KIND>
 __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
-                                         Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
+                                         Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5, double& s5)
 {
     const Deriv<double>& k1 = R.k;
     const double a = R.a;
     Deriv<double> k2, k3, k4, k5, k6;
     double Hd, cd;
     const auto sc = sincos_source<KIND>();
+    // stages 2-6 take sin and cos of their polar angle from the step's start
+    // where it is within 1/16 and within half of |sin(theta0)| of it (the
+    // latter keeps the sine's relative accuracy near the poles)
+    const double dmax = fmin(0.0625, 0.5 * fabs(R.sth));
+    const ShiftLoad shift{opaque_const((ConstDouble*)kShift64Const)};
+#define TT_RHS(th_, r_, pr_, pth_, k_) \
+    M.rhs_near(a, r_, th_, R.th, R.sth, R.cth, dmax, pr_, pth_, R.pt, R.pph, k_, Hd, cd, sc, shift)
     Dp45Source<KIND == 0> K;
     K.next();
     {
         const double A21 = K[0];
-        M.rhs(a, fma(h, A21 * k1.r, R.r), fma(h, A21 * k1.th, R.th), fma(h, A21 * k1.pr, R.pr),
-              fma(h, A21 * k1.pth, R.pth), R.pt, R.pph, k2, Hd, cd, sc);
+        TT_RHS(fma(h, A21 * k1.th, R.th), fma(h, A21 * k1.r, R.r), fma(h, A21 * k1.pr, R.pr),
+               fma(h, A21 * k1.pth, R.pth), k2);
     }
     K.next();
     {
         const double A31 = K[1], A32 = K[2];
 #define TT_S3(c) fma(h, fma(A32, k2.c, A31 * k1.c), R.c)
-        M.rhs(a, TT_S3(r), TT_S3(th), TT_S3(pr), TT_S3(pth), R.pt, R.pph, k3, Hd, cd, sc);
+        TT_RHS(TT_S3(th), TT_S3(r), TT_S3(pr), TT_S3(pth), k3);
     }
     K.next();
     {
         const double A41 = K[3], A42 = K[4], A43 = K[5];
 #define TT_S4(c) fma(h, fma(A43, k3.c, fma(A42, k2.c, A41 * k1.c)), R.c)
-        M.rhs(a, TT_S4(r), TT_S4(th), TT_S4(pr), TT_S4(pth), R.pt, R.pph, k4, Hd, cd, sc);
+        TT_RHS(TT_S4(th), TT_S4(r), TT_S4(pr), TT_S4(pth), k4);
     }
     K.next();
     {
         const double A51 = K[6], A52 = K[7], A53 = K[8], A54 = K[9];
 #define TT_S5(c) fma(h, fma(A54, k4.c, fma(A53, k3.c, fma(A52, k2.c, A51 * k1.c))), R.c)
-        M.rhs(a, TT_S5(r), TT_S5(th), TT_S5(pr), TT_S5(pth), R.pt, R.pph, k5, Hd, cd, sc);
+        TT_RHS(TT_S5(th), TT_S5(r), TT_S5(pr), TT_S5(pth), k5);
     }
     K.next();
     {
         const double A61 = K[10], A62 = K[11], A63 = K[12], A64 = K[13], A65 = K[14];
 #define TT_S6(c) fma(h, fma(A65, k5.c, fma(A64, k4.c, fma(A63, k3.c, fma(A62, k2.c, A61 * k1.c)))), R.c)
-        M.rhs(a, TT_S6(r), TT_S6(th), TT_S6(pr), TT_S6(pth), R.pt, R.pph, k6, Hd, cd, sc);
+        TT_RHS(TT_S6(th), TT_S6(r), TT_S6(pr), TT_S6(pth), k6);
     }
     K.next();
     {
@@ -765,7 +809,8 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
         y5.pr = TT_Y5(pr);
         y5.pth = TT_Y5(pth);
     }
-    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, sc);
+    // the step's end from its own angle: the next step starts from its sin and cos
+    M.rhs_sc(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, s5, sc);
     K.next();
     {
         const double E1 = K[20], E3 = K[21], E4 = K[22], E5 = K[23], E6 = K[24], E7 = K[25];
@@ -777,6 +822,7 @@ __device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M,
         e.pr = TT_E(pr);
         e.pth = TT_E(pth);
     }
+#undef TT_RHS
 #undef TT_S3
 #undef TT_S4
 #undef TT_S5
@@ -815,7 +861,7 @@ __device__ __forceinline__ void six_stage(const Ray& R, const MetricOps<KIND>& M
 
 template <int KIND, int M>
 __device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>& M_, double h, Deriv<double>& y5,
-                                             Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5)
+                                             Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5, double& s5)
 {
     using P = Pair<M>;
     // component-wise stage derivatives k.c[stage] for the dynamic components
@@ -835,7 +881,7 @@ __device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>
     y5.ph = fma(h, weighted<B>(k.ph), R.ph);
     y5.pr = fma(h, weighted<B>(k.pr), R.pr);
     y5.pth = fma(h, weighted<B>(k.pth), R.pth);
-    M_.rhs(R.a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, sc);
+    M_.rhs_sc(R.a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, s5, sc);
     using E = RowE<P>;
     e.t = h * weighted<E>(k.t);
     e.r = h * weighted<E>(k.r);
@@ -906,7 +952,7 @@ __device__ __forceinline__ double gbs_floor(double e, double big, double y0, dou
 template <int KIND>
 __device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>& M, double h, double atol,
                                              double rtol, Deriv<double>& y5, Deriv<double>& k7, Deriv<double>& e,
-                                             double& H5, double& c5)
+                                             double& H5, double& c5, double& s5)
 {
     constexpr int K = kGbsColumns;
     const double a = R.a;
@@ -966,7 +1012,7 @@ __device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>
     e.ph = gbs_floor(Tph[K - 1] - Tph[K - 2], bph, R.ph, y5.ph, atol, rtol);
     e.pr = gbs_floor(Tpr[K - 1] - Tpr[K - 2], bpr, R.pr, y5.pr, atol, rtol);
     e.pth = gbs_floor(Tpth[K - 1] - Tpth[K - 2], bpth, R.pth, y5.pth, atol, rtol);
-    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+    M.rhs_sc(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, s5);
 }
 
 // Verlet (Sec. 3.2): a fixed step of the generalized Stormer-Verlet scheme for
@@ -987,7 +1033,7 @@ constexpr double kVerletTol = 1e-14;
 
 template <int KIND>
 __device__ __forceinline__ bool stages_verlet(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
-                                              Deriv<double>& k7, double& H5, double& c5)
+                                              Deriv<double>& k7, double& H5, double& c5, double& s5)
 {
     const double a = R.a, hh = 0.5 * h;
     Deriv<double> d;
@@ -1034,7 +1080,7 @@ __device__ __forceinline__ bool stages_verlet(const Ray& R, const MetricOps<KIND
     y5.ph = xph;
     y5.pr = fma(hh, d.pr, pr);
     y5.pth = fma(hh, d.pth, pth);
-    M.rhs(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5);
+    M.rhs_sc(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, s5);
     return true;
 }
 
@@ -1160,7 +1206,7 @@ __device__ __forceinline__ void gbs_search_start(GbsSearch& S, double s0)
 
 // The ray moves to the end of its accepted step.
 __device__ __forceinline__ void advance(Ray& R, double h, double fac, const Deriv<double>& y5, const Deriv<double>& k7,
-                                        double c5, bool used32)
+                                        double c5, double s5, bool used32)
 {
     R.lam += h;
     R.t = y5.t;
@@ -1172,6 +1218,7 @@ __device__ __forceinline__ void advance(Ray& R, double h, double fac, const Deri
     R.k = k7;
     R.k32 = used32 ? 1 : 0;
     R.cth = c5;
+    R.sth = s5;
     R.h = h * fac;
     R.rej_prev = 0;
 }
@@ -1179,11 +1226,10 @@ __device__ __forceinline__ void advance(Ray& R, double h, double fac, const Deri
 // One probe of an event search, with the solution y at s and its slope k.
 // Returns true when the ray has ended.
 __device__ bool gbs_probe(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySettings& P, const Deriv<double>& y,
-                          const Deriv<double>& k,
-                          double c)
+                          const Deriv<double>& k, double c, double s_end)
 {
     if (S.phase == 3) {
-        advance(R, S.h, S.fac, y, k, c, false);
+        advance(R, S.h, S.fac, y, k, c, s_end, false);
         S.phase = 0;
         return false;
     }
@@ -1276,36 +1322,36 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
     }
     const double h = probe ? S.s * S.h : R.h;
     Deriv<double> y5, k7, e;
-    double H5, c5;
+    double H5, c5, s5;
     bool used32 = false;
     double fac = 1.0;
     if constexpr (METHOD == METHOD_VERLET) {
         // fixed step, no error control: a converged step is always taken
-        if (!stages_verlet<KIND>(R, M, h, y5, k7, H5, c5)) {
+        if (!stages_verlet<KIND>(R, M, h, y5, k7, H5, c5, s5)) {
             ray_fail(R, A);
             return true;
         }
     } else {
         if (PREC == 1 && KIND == 0 && far_field(R, A, P)) {
-            stages32(R, h, y5, k7, e, H5, c5);
+            stages32(R, h, y5, k7, e, H5, c5, s5);
             used32 = true;
         } else {
             if (PREC == 1 && R.k32) {
                 // leaving the FP32 regime: re-evaluate the first stage in FP64
                 double Hd;
-                M.rhs(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth);
+                M.rhs_sc(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth, R.sth);
                 R.k32 = 0;
             }
             if constexpr (METHOD == METHOD_DP45)
-                stages64<KIND>(R, M, h, y5, k7, e, H5, c5);
+                stages64<KIND>(R, M, h, y5, k7, e, H5, c5, s5);
             else if constexpr (METHOD == METHOD_GBS)
                 // one call site for attempts and probes (a probe has no error control)
-                stages64_gbs<KIND>(R, M, h, probe ? 0.0 : P.atol, probe ? 0.0 : P.rtol, y5, k7, e, H5, c5);
+                stages64_gbs<KIND>(R, M, h, probe ? 0.0 : P.atol, probe ? 0.0 : P.rtol, y5, k7, e, H5, c5, s5);
             else
-                stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5);
+                stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5, s5);
         }
         if constexpr (METHOD == METHOD_GBS) {
-            if (probe) return gbs_probe(R, S, A, P, y5, k7, c5);
+            if (probe) return gbs_probe(R, S, A, P, y5, k7, c5, s5);
         }
         R.n_f32 += used32 ? 1 : 0;
         const double atol = P.atol, rtol = P.rtol;
@@ -1404,7 +1450,7 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
         }
     }
 
-    advance(R, h, fac, y5, k7, c5, used32);
+    advance(R, h, fac, y5, k7, c5, s5, used32);
     return false;
 }
 

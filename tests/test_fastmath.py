@@ -18,6 +18,9 @@ extern "C" void run(const double* x, double* s, double* c, long n) {
 extern "C" void run32(const float* x, float* s, float* c, long n) {
     for (long i = 0; i < n; ++i) tartarus::sincos32(x[i], s + i, c + i);
 }
+extern "C" void shift(const double* s0, const double* c0, const double* dt, double* s, double* c, long n) {
+    for (long i = 0; i < n; ++i) tartarus::sincos_shift(s0[i], c0[i], dt[i], s[i], c[i], tartarus::ShiftImm{});
+}
 """
 
 
@@ -34,6 +37,7 @@ def lib():
     L.run.argtypes = [dp, dp, dp, C.c_long]
     fp = C.POINTER(C.c_float)
     L.run32.argtypes = [fp, fp, fp, C.c_long]
+    L.shift.argtypes = [dp, dp, dp, dp, dp, C.c_long]
     return L
 
 
@@ -104,3 +108,41 @@ def test_sincos_wide_arguments_and_quadrants(lib):
     assert set((k[k < 0] % 4).tolist()) == {0, 1, 2, 3} and set((k[k > 0] % 4).tolist()) == {0, 1, 2, 3}
     s0, c0 = run(lib, np.array([0.0, -0.0]))
     assert np.all(s0 == 0.0) and np.all(c0 == 1.0)
+
+
+def test_angle_shift_accuracy(lib):
+    """sin and cos of theta0 + d from those of theta0 (the integrator's stages
+    near the step's start), for |d| <= 1/16 and |d| <= |sin(theta0)| / 2, the
+    bounds the kernel applies, given correctly rounded sin and cos of theta0;
+    theta0 + d is exact, as the stage angle minus the step's start is in the
+    kernel.  Against the C library: within 2 ulp where |sin|, |cos| >= 0.1;
+    the sine within 3 ulp relative next to both poles (where 1/sin^2 enters the
+    right-hand side); everywhere within one ulp of 1 absolute, which near the
+    equator is the cosine's own uncertainty from rounding theta (ulp(pi/2))."""
+    rng = np.random.default_rng(3)
+    n = 200000
+    th = np.concatenate([rng.uniform(0.002, np.pi - 0.002, n), rng.uniform(-0.5, 3.6, n // 4),
+                         rng.uniform(0.0005, 0.05, n // 8), np.pi - rng.uniform(0.0005, 0.05, n // 8),
+                         np.array([np.pi / 2, np.pi / 2 + 1e-12, 0.05, np.pi - 0.05])])
+    lim = np.minimum(1.0 / 16.0, 0.5 * np.abs(np.sin(th)))
+    d = rng.uniform(-1.0, 1.0, th.size) * lim
+    d[-4:] = [1.0 / 16.0, -1.0 / 16.0, 0.025, -0.025]
+    th1 = th + d
+    d = th1 - th                  # exact: the shifted angle is th1 itself
+    s0, c0 = np.sin(th), np.cos(th)
+    s, c = np.zeros_like(th), np.zeros_like(th)
+    p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    lib.shift(p(s0), p(c0), p(d), p(s), p(c), th.size)
+    es, ec = np.sin(th1), np.cos(th1)
+    us = np.abs(s - es) / np.spacing(np.abs(es))
+    uc = np.abs(c - ec) / np.spacing(np.abs(ec))
+    assert us[np.abs(es) >= 0.1].max() <= 2.0 and uc[np.abs(ec) >= 0.1].max() <= 2.0
+    assert np.abs(s - es).max() < 2.3e-16 and np.abs(c - ec).max() < 2.3e-16
+    poles = ((np.abs(th1) < 0.05) | (np.abs(th1 - np.pi) < 0.05)) & (es != 0.0)
+    assert poles.sum() > 10000 and us[poles].max() <= 3.0
+    # beyond its bound the shift is not used: at |d| = 1/4 its error is far above an ulp
+    s2, c2 = np.zeros(1), np.zeros(1)
+    t0 = np.array([1.0])
+    dd = np.array([0.25])
+    lib.shift(p(np.sin(t0)), p(np.cos(t0)), p(dd), p(s2), p(c2), 1)
+    assert abs(s2[0] - np.sin(1.25)) > 1e-14
