@@ -66,7 +66,7 @@ __device__ __forceinline__ double kerr_H64(double a, double r, double th, double
     const double del = fma(r, r - 2.0, a2);
     const double P = fma(r2 + a2, pt, a * pph);
     const double W = fma(a * s2, pt, pph);
-    const double K = fma(del * pr, pr, fma(pth, pth, W * W * rcp64(s2) - P * P * rcp64(del)));
+    const double K = fma(del * pr, pr, fma(pth, pth, fma(W * W, rcp64(s2), -(P * P * rcp64(del)))));
     cth = c;
     sth = s;
     return 0.5 * K * rcp64(sig);

@@ -144,18 +144,35 @@ struct Ray {
 // tolerances and precisions share the epoch.
 struct RaySettings {
     double rtol, atol, horizon_factor, r_escape, event_tol;
-    long long max_steps;
+    int max_steps;   // attempts allowed, clamped to the int range (attempts are counted in int)
     int allow32;   // mixed precision: FP32 stages allowed where the regime test passes
 };
 
+__device__ __forceinline__ int clamp_steps(long long n)
+{
+    return n > 0x7fffffffLL ? 0x7fffffff : (int)n;
+}
+
 __device__ __forceinline__ RaySettings launch_settings(const LaunchArgs& A)
 {
-    return {A.rtol, A.atol, A.horizon_factor, A.r_escape, A.event_tol, A.max_steps, 1};
+    return {A.rtol, A.atol, A.horizon_factor, A.r_escape, A.event_tol, clamp_steps(A.max_steps), 1};
 }
 
 __device__ __forceinline__ RaySettings job_settings(const DevJob& J)
 {
-    return {J.rtol, J.atol, J.horizon_factor, J.r_escape, J.event_tol, J.max_steps, J.allow32};
+    return {J.rtol, J.atol, J.horizon_factor, J.r_escape, J.event_tol, clamp_steps(J.max_steps), J.allow32};
+}
+
+// max(|a|, |b|) in one instruction.  fmax of values the compiler cannot prove
+// canonical (loop-carried state) first canonicalizes one operand, a second
+// instruction; the operands here come from arithmetic, so they are never
+// signalling NaNs, and for a quiet NaN the hardware maximum returns the other
+// operand, as fmax does.
+__device__ __forceinline__ double max_abs(double a, double b)
+{
+    double m;
+    asm("v_max_f64 %0, |%1|, |%2|" : "=v"(m) : "v"(a), "v"(b));
+    return m;
 }
 
 template <int KIND>
@@ -442,7 +459,7 @@ __device__ bool ray_init(Ray& R, long long gid, const LaunchArgs& A, const JobDi
     R.rp = C.rp;
     R.k32 = 0;
     // Carter's constant from the initial state sets the polar turning-point guard
-    const double Q = fma(R.pth, R.pth, C.c2_obs * (R.pph * R.pph * C.is2_obs - R.a * R.a * R.pt * R.pt));
+    const double Q = fma(R.pth, R.pth, C.c2_obs * fma(R.pph * R.pph, C.is2_obs, -(R.a * R.a * R.pt * R.pt)));
     R.guard_th = (float)(A.turn_th * sqrt(fmax(Q, 1e-12)));
     R.guard_r = (float)(A.turn_r * fabs(R.pt));
     double H;
@@ -934,7 +951,7 @@ constexpr double kGbsFloorTol = 0.01;
 
 __device__ __forceinline__ double gbs_floor(double e, double big, double y0, double y1, double atol, double rtol)
 {
-    const double fl = fmin(kGbsFloorUlps * 0x1p-52 * big, kGbsFloorTol * fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
+    const double fl = fmin(kGbsFloorUlps * 0x1p-52 * big, kGbsFloorTol * fma(rtol, max_abs(y0, y1), atol));
     return fabs(e) <= fl ? 0.0 : e;
 }
 
@@ -1084,10 +1101,19 @@ __device__ __forceinline__ bool stages_verlet(const Ray& R, const MetricOps<KIND
     return true;
 }
 
-__device__ __forceinline__ double sq_ratio(double e, double y0, double y1, double atol, double rtol)
+// Scaled error of one component, e / (atol + rtol max(|y0|, |y1|)).
+__device__ __forceinline__ double err_ratio(double e, double y0, double y1, double atol, double rtol)
 {
-    const double z = e * rcp64_coarse(fma(rtol, fmax(fabs(y0), fabs(y1)), atol));
-    return z * z;
+    return e * rcp64_coarse(fma(rtol, max_abs(y0, y1), atol));
+}
+
+// Sum of squares of the six scaled errors, the first squared and the others
+// added by fused multiply-adds in this order.  (Written out, z0 z0 + z1 z1 lets
+// the compiler fuse either product, and which one it picks can change with
+// unrelated code; the explicit form rounds the same in every build.)
+__device__ __forceinline__ double sum_sq6(double z0, double z1, double z2, double z3, double z4, double z5)
+{
+    return fma(z5, z5, fma(z4, z4, fma(z3, z3, fma(z2, z2, fma(z1, z1, z0 * z0)))));
 }
 
 // Rounding floor of an embedded pair's error estimate.  The estimate
@@ -1113,16 +1139,15 @@ struct PairErrNorm1 {
     static constexpr double value = sum(0);
 };
 
-// Squared scaled error of one component, with the rounding floor: zero when
+// Scaled error of one component with the rounding floor: zero when
 // |e| <= min(c max(|k0|, |k1|), kPairFloorTol sc), c = kPairFloorUlps ulp
 // |b - b*|_1 |h|.
-__device__ __forceinline__ double sq_ratio_floor(double e, double c, double k0, double k1, double y0, double y1,
-                                                 double atol, double rtol)
+__device__ __forceinline__ double err_ratio_floor(double e, double c, double k0, double k1, double y0, double y1,
+                                                  double atol, double rtol)
 {
-    const double sc = fma(rtol, fmax(fabs(y0), fabs(y1)), atol);
-    const double fl = fmin(c * fmax(fabs(k0), fabs(k1)), kPairFloorTol * sc);
-    const double z = fabs(e) <= fl ? 0.0 : e * rcp64_coarse(sc);
-    return z * z;
+    const double sc = fma(rtol, max_abs(y0, y1), atol);
+    const double fl = fmin(c * max_abs(k0, k1), kPairFloorTol * sc);
+    return fabs(e) <= fl ? 0.0 : e * rcp64_coarse(sc);
 }
 
 // y^N for a compile-time N >= 1 by repeated squaring.
@@ -1316,7 +1341,7 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
 {
     bool probe = false;
     if constexpr (METHOD == METHOD_GBS) probe = S.phase != 0;
-    if (!probe && (long long)R.n_acc + R.n_rej >= P.max_steps) {
+    if (!probe && R.n_acc + R.n_rej >= P.max_steps) {
         ray_fail(R, A);
         return true;
     }
@@ -1358,20 +1383,17 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
         double acc;
         if constexpr (METHOD == METHOD_GBS) {
             // (the extrapolation applies its own floor in stages64_gbs)
-            acc = sq_ratio(e.t, R.t, y5.t, atol, rtol);
-            acc += sq_ratio(e.r, R.r, y5.r, atol, rtol);
-            acc += sq_ratio(e.th, R.th, y5.th, atol, rtol);
-            acc += sq_ratio(e.ph, R.ph, y5.ph, atol, rtol);
-            acc += sq_ratio(e.pr, R.pr, y5.pr, atol, rtol);
-            acc += sq_ratio(e.pth, R.pth, y5.pth, atol, rtol);
+            acc = sum_sq6(err_ratio(e.t, R.t, y5.t, atol, rtol), err_ratio(e.r, R.r, y5.r, atol, rtol),
+                          err_ratio(e.th, R.th, y5.th, atol, rtol), err_ratio(e.ph, R.ph, y5.ph, atol, rtol),
+                          err_ratio(e.pr, R.pr, y5.pr, atol, rtol), err_ratio(e.pth, R.pth, y5.pth, atol, rtol));
         } else {
             const double c = kPairFloorUlps * 0x1p-52 * PairErrNorm1<METHOD>::value * fabs(h);
-            acc = sq_ratio_floor(e.t, c, R.k.t, k7.t, R.t, y5.t, atol, rtol);
-            acc += sq_ratio_floor(e.r, c, R.k.r, k7.r, R.r, y5.r, atol, rtol);
-            acc += sq_ratio_floor(e.th, c, R.k.th, k7.th, R.th, y5.th, atol, rtol);
-            acc += sq_ratio_floor(e.ph, c, R.k.ph, k7.ph, R.ph, y5.ph, atol, rtol);
-            acc += sq_ratio_floor(e.pr, c, R.k.pr, k7.pr, R.pr, y5.pr, atol, rtol);
-            acc += sq_ratio_floor(e.pth, c, R.k.pth, k7.pth, R.pth, y5.pth, atol, rtol);
+            acc = sum_sq6(err_ratio_floor(e.t, c, R.k.t, k7.t, R.t, y5.t, atol, rtol),
+                          err_ratio_floor(e.r, c, R.k.r, k7.r, R.r, y5.r, atol, rtol),
+                          err_ratio_floor(e.th, c, R.k.th, k7.th, R.th, y5.th, atol, rtol),
+                          err_ratio_floor(e.ph, c, R.k.ph, k7.ph, R.ph, y5.ph, atol, rtol),
+                          err_ratio_floor(e.pr, c, R.k.pr, k7.pr, R.pr, y5.pr, atol, rtol),
+                          err_ratio_floor(e.pth, c, R.k.pth, k7.pth, R.pth, y5.pth, atol, rtol));
         }
         // p_t and p_phi have zero error (their derivatives vanish identically)
         const double err2 = acc * 0.125;   // squared RMS error over the 8 components
@@ -1402,8 +1424,8 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
 
     // ---- constraint residual (Eq. (17)) at the accepted state
     const double aH = fabs(H5);
-    R.hmax = fmax(R.hmax, aH);
-    if (y5.r >= 1.5 * R.rp) R.hgate = fmax(R.hgate, aH);
+    R.hmax = max_abs(R.hmax, aH);   // (both non-negative)
+    if (y5.r >= 1.5 * R.rp) R.hgate = max_abs(R.hgate, aH);
 
     // ---- events on the accepted step [lam, lam + h]
     double r_stop = P.horizon_factor * R.rp;

@@ -389,6 +389,22 @@ def test_launch_shape_invariance_other_methods(T, method):
             assert np.array_equal(ref[k], g[k]), (method, shape, k)
 
 
+def test_launch_shape_invariance_mixed(T):
+    """Mixed precision at rtol 1e-8, where most far-field attempts take FP32
+    stages: the same bits for every launch shape and queue order (the regime
+    is each ray's own decision, so a lane's neighbours never enter it)."""
+    w = W.WORKLOADS["kerr09_512"]
+    cam = dict(w["cameras"][0], nx=72, ny=56)
+    ref = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], 1, launch=T.make_launch(order=T.ORDER_PIXEL))
+    assert (ref["n_fp32"] > 0).mean() > 0.5
+    for shape in ((64, 2, 16, 1, T.ORDER_COST), (256, 1, 1, 4, T.ORDER_TILE), (128, 0, 64, 8, T.ORDER_DEFAULT),
+                  (256, 3, 1, 4, T.ORDER_COST)):
+        say("mixed launch", shape)
+        g = gpu_trace(T, w["a"], cam, w["disk"], w["solver"], 1, launch=T.make_launch(*shape))
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (shape, k)
+
+
 def test_tile_order_ragged_cameras(T):
     """8 x 8 tile order on cameras whose sides are not multiples of 8 (edge
     tiles are smaller), three cameras in one trace: every pixel is traced once
