@@ -55,11 +55,17 @@ struct ShiftImm {
 // must be zero).
 TT_HD inline double flip_sign(double x, unsigned hi_bit)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    // one XOR on the high word (through a 64-bit integer the compiler split
+    // the XOR into byte-wise masks, three instructions)
+    return __hiloint2double(__double2hiint(x) ^ (int)hi_bit, __double2loint(x));
+#else
     unsigned long long u;
     std::memcpy(&u, &x, sizeof u);
     u ^= (unsigned long long)hi_bit << 32;
     std::memcpy(&x, &u, sizeof u);
     return x;
+#endif
 }
 
 // The reduced argument's sine and cosine (sr, cr) and the quadrant q: with

@@ -1182,17 +1182,16 @@ __device__ __forceinline__ double pow_m_inv(double x)
 // Step-size factor of the elementary controller from the squared error norm
 // err2 = err^2: min(fmx, max(0.2, 0.9 err^(-1/P))) = min(fmx, max(0.2,
 // 0.9 err2^(-1/(2P)))), P = 5 for the 5(4) pairs and 2K - 1 for the
-// extrapolation (working on err^2 saves the square root).  Below lo^2 and
-// above hi^2 the clamps decide the result without the power
-// (0.9 lo^(-1/P) >= 10 and 0.9 hi^(-1/P) <= 0.2).
+// extrapolation (working on err^2 saves the square root).  The power is taken
+// of err2 clamped to [1e-24, 1e16], the range its estimate covers: at the ends
+// 0.9 err2^(-1/(2P)) is at least 11 and at most 0.17 for both P, beyond the
+// factor's own clamps, so clamping err2 never changes the factor and no branch
+// is needed.  A NaN err2 is the caller's case.
 template <int P>
 __device__ __forceinline__ double step_factor(double err2, double fmx)
 {
-    constexpr double lo = P == 5 ? 1e-6 : 1e-12;
-    constexpr double hi = P == 5 ? 1e5 : 1e8;
-    if (err2 < lo * lo) return fmx;
-    if (err2 > hi * hi) return 0.2;
-    return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<2 * P>(err2)));
+    const double x = fmin(fmax(err2, 1e-24), 1e16);
+    return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<2 * P>(x)));
 }
 
 // Event search of the extrapolation.  A macro-step spans up to hundreds of M,
