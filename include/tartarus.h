@@ -271,7 +271,7 @@ int tartarus_trace_launch(const tartarus_metric* metric, const tartarus_camera* 
  * with the same arguments (same kernels). */
 #define TARTARUS_NOALLOC_MAX_RAYS 262144
 #define TARTARUS_NOALLOC_MAX_CAMERAS 64
-#define TARTARUS_NOALLOC_SCRATCH_BYTES (135559680ull)   /* 129.3 MiB */
+#define TARTARUS_NOALLOC_SCRATCH_BYTES (135561216ull)   /* 129.3 MiB */
 int tartarus_trace_noalloc(const tartarus_metric* metric, const tartarus_camera* cams, int ncams,
                            const tartarus_disk* disk, const tartarus_solver* solver,
                            const tartarus_outputs* out, const tartarus_launch* launch, void* hip_stream);

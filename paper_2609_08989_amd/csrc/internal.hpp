@@ -86,6 +86,9 @@ struct JobConst {
     double rp;                      // horizon radius r_+
     double r_in, x0;                // disk inner edge (r_ISCO if not given) and sqrt(r_in)
     double xi[3], coef[3];          // roots of x^3 - 3x + 2a and their Page-Thorne coefficients
+    double a2;                      // a^2
+    double gate_r;                  // 1.5 r_+: the constraint gate counts states at r >= gate_r
+    double r_stop;                  // horizon event radius: horizon_factor r_+ (tabulated: at least the table's r_min)
 };
 
 // Per-launch uniform parameters.

@@ -17,6 +17,18 @@
 
 namespace tartarus {
 
+// The spin a and its square.  A trace of one metric takes both from the
+// launch, wave-uniform in scalar registers, so a^2 is not formed again in every
+// right-hand side; a ray of a serving epoch carries its own.
+struct Spin {
+    double a, a2;
+};
+
+__device__ __forceinline__ Spin spin_of(double a)
+{
+    return {a, a * a};
+}
+
 // d/dlambda of (t, r, theta, phi, p_r, p_theta); p_t and p_phi are constant.
 template <typename T>
 struct Deriv {
@@ -25,10 +37,10 @@ struct Deriv {
 
 // FP64 right-hand side from sin^2(theta) s2, cos^2(theta) c2 and
 // sin(theta) cos(theta) sc; also returns H (Eq. (1)).
-__device__ __forceinline__ void kerr_rhs64_trig(double a, double r, double s2, double c2, double sc, double pr,
+__device__ __forceinline__ void kerr_rhs64_trig(Spin sp, double r, double s2, double c2, double sc, double pr,
                                                 double pth, double pt, double pph, Deriv<double>& d, double& H)
 {
-    const double a2 = a * a;
+    const double a = sp.a, a2 = sp.a2;
     const double r2 = r * r;
     const double sig = fma(a2, c2, r2);
     const double del = fma(r, r - 2.0, a2);
@@ -65,7 +77,7 @@ __device__ __forceinline__ void kerr_rhs64_trig(double a, double r, double s2, d
 // and sin(theta) of the point.  coef supplies the sincos64 coefficients
 // (compile-time immediates by default).
 template <class Coef = SinCosImm>
-__device__ __forceinline__ void kerr_rhs64(double a, double r, double th, double pr, double pth, double pt,
+__device__ __forceinline__ void kerr_rhs64(Spin a, double r, double th, double pr, double pth, double pt,
                                            double pph, Deriv<double>& d, double& H, double& cth, double& sth,
                                            Coef coef = {})
 {

@@ -148,6 +148,22 @@ struct RaySettings {
     int allow32;   // mixed precision: FP32 stages allowed where the regime test passes
 };
 
+// What every ray of a one-shot trace shares (one metric, one solver), read
+// once per wavefront from the first job's constants, so it stays in scalar
+// registers: the spin and its square, the radius from which the constraint
+// gate counts and the horizon event's radius.  Serving epochs form these per
+// ray from the ray's own request.
+struct TraceUniform {
+    Spin spin;
+    double gate_r, r_stop;
+};
+
+__device__ __forceinline__ TraceUniform trace_uniform(const LaunchArgs& A)
+{
+    const JobConst& C = A.jc[0];
+    return {{A.jobs[0].a, C.a2}, C.gate_r, C.r_stop};
+}
+
 __device__ __forceinline__ int clamp_steps(long long n)
 {
     return n > 0x7fffffffLL ? 0x7fffffff : (int)n;
@@ -182,7 +198,7 @@ struct MetricOps {
     // coefficients from (immediates unless a stage loop passes SinCosLoad)
     // Right-hand side at (r, th, pr, pth); also H, cos(th) and sin(th).
     template <class Coef = SinCosImm>
-    __device__ __forceinline__ void rhs_sc(double a, double r, double th, double pr, double pth, double pt, double pph,
+    __device__ __forceinline__ void rhs_sc(Spin a, double r, double th, double pr, double pth, double pt, double pph,
                                            Deriv<double>& d, double& H, double& c, double& s, Coef coef = {}) const
     {
         if (KIND == 0)
@@ -191,7 +207,7 @@ struct MetricOps {
             table_rhs64(T, r, th, pr, pth, pt, pph, d, H, c, s);
     }
     template <class Coef = SinCosImm>
-    __device__ __forceinline__ void rhs(double a, double r, double th, double pr, double pth, double pt, double pph,
+    __device__ __forceinline__ void rhs(Spin a, double r, double th, double pr, double pth, double pt, double pph,
                                         Deriv<double>& d, double& H, double& c, Coef coef = {}) const
     {
         double s;
@@ -202,7 +218,7 @@ struct MetricOps {
     // cos of th from those of th0 by the angle-sum identities, elsewhere from
     // th itself.  Returns cos(th) in c.
     template <class Coef, class Shift>
-    __device__ __forceinline__ void rhs_near(double a, double r, double th, double th0, double s0, double c0,
+    __device__ __forceinline__ void rhs_near(Spin a, double r, double th, double th0, double s0, double c0,
                                              double dmax, double pr, double pth, double pt, double pph,
                                              Deriv<double>& d, double& H, double& c, Coef coef, Shift shift) const
     {
@@ -259,6 +275,10 @@ __global__ void job_setup(const DevJob* jobs, JobConst* jc, int njobs, const dou
     C.r_in = J.disk_r_in > 0.0 ? J.disk_r_in : isco_radius(J.a);
     C.x0 = sqrt(C.r_in);
     nt_flux_constants(J.a, C.xi, C.coef);
+    C.a2 = J.a * J.a;
+    C.gate_r = 1.5 * C.rp;
+    C.r_stop = J.horizon_factor * C.rp;
+    if (KIND == 1 && r_min > C.r_stop) C.r_stop = r_min;
     jc[j] = C;
 }
 
@@ -463,7 +483,7 @@ __device__ bool ray_init(Ray& R, long long gid, const LaunchArgs& A, const JobDi
     R.guard_th = (float)(A.turn_th * sqrt(fmax(Q, 1e-12)));
     R.guard_r = (float)(A.turn_r * fabs(R.pt));
     double H;
-    M.rhs_sc(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, H, R.cth, R.sth);
+    M.rhs_sc(spin_of(R.a), R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, H, R.cth, R.sth);
     R.hmax = fabs(H);
     R.hgate = R.r >= 1.5 * R.rp ? fabs(H) : 0.0;
     R.lam = 0.0;
@@ -769,11 +789,10 @@ __device__ __forceinline__ auto sincos_source()
         return SinCosImm{};
 }
 template <int KIND>
-__device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
+__device__ __forceinline__ void stages64(const Ray& R, const MetricOps<KIND>& M, Spin a, double h, Deriv<double>& y5,
                                          Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5, double& s5)
 {
     const Deriv<double>& k1 = R.k;
-    const double a = R.a;
     Deriv<double> k2, k3, k4, k5, k6;
     double Hd, cd;
     const auto sc = sincos_source<KIND>();
@@ -858,13 +877,13 @@ struct SixSlopes {
 // Stages S..5 of a six-stage pair: the stage argument from the compile-time
 // row a[S] (zero weights drop out), then its slope.
 template <int KIND, class P, int S, class Coef>
-__device__ __forceinline__ void six_stage(const Ray& R, const MetricOps<KIND>& M_, double h, SixSlopes& k, Coef sc)
+__device__ __forceinline__ void six_stage(const Ray& R, const MetricOps<KIND>& M_, Spin a, double h, SixSlopes& k, Coef sc)
 {
     if constexpr (S < 6) {
         using W = RowA<P, S>;
         Deriv<double> ks;
         double Hd, cd;
-        M_.rhs(R.a, fma(h, weighted<W>(k.r), R.r), fma(h, weighted<W>(k.th), R.th), fma(h, weighted<W>(k.pr), R.pr),
+        M_.rhs(a, fma(h, weighted<W>(k.r), R.r), fma(h, weighted<W>(k.th), R.th), fma(h, weighted<W>(k.pr), R.pr),
                fma(h, weighted<W>(k.pth), R.pth), R.pt, R.pph, ks, Hd, cd, sc);
         k.t[S] = ks.t;
         k.r[S] = ks.r;
@@ -872,12 +891,12 @@ __device__ __forceinline__ void six_stage(const Ray& R, const MetricOps<KIND>& M
         k.ph[S] = ks.ph;
         k.pr[S] = ks.pr;
         k.pth[S] = ks.pth;
-        six_stage<KIND, P, S + 1>(R, M_, h, k, sc);
+        six_stage<KIND, P, S + 1>(R, M_, a, h, k, sc);
     }
 }
 
 template <int KIND, int M>
-__device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>& M_, double h, Deriv<double>& y5,
+__device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>& M_, Spin a, double h, Deriv<double>& y5,
                                              Deriv<double>& k7, Deriv<double>& e, double& H5, double& c5, double& s5)
 {
     using P = Pair<M>;
@@ -890,7 +909,7 @@ __device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>
     k.pr[0] = R.k.pr;
     k.pth[0] = R.k.pth;
     const auto sc = sincos_source<KIND>();
-    six_stage<KIND, P, 1>(R, M_, h, k, sc);
+    six_stage<KIND, P, 1>(R, M_, a, h, k, sc);
     using B = RowB<P>;
     y5.t = fma(h, weighted<B>(k.t), R.t);
     y5.r = fma(h, weighted<B>(k.r), R.r);
@@ -898,7 +917,7 @@ __device__ __forceinline__ void stages64_six(const Ray& R, const MetricOps<KIND>
     y5.ph = fma(h, weighted<B>(k.ph), R.ph);
     y5.pr = fma(h, weighted<B>(k.pr), R.pr);
     y5.pth = fma(h, weighted<B>(k.pth), R.pth);
-    M_.rhs_sc(R.a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, s5, sc);
+    M_.rhs_sc(a, y5.r, y5.th, y5.pr, y5.pth, R.pt, R.pph, k7, H5, c5, s5, sc);
     using E = RowE<P>;
     e.t = h * weighted<E>(k.t);
     e.r = h * weighted<E>(k.r);
@@ -967,12 +986,11 @@ __device__ __forceinline__ double gbs_floor(double e, double big, double y0, dou
 // kGbsColumns entries per row: entries past the row's own take a zero weight
 // and copy their left neighbour, so register indices stay compile-time.
 template <int KIND>
-__device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>& M, double h, double atol,
+__device__ __forceinline__ void stages64_gbs(const Ray& R, const MetricOps<KIND>& M, Spin a, double h, double atol,
                                              double rtol, Deriv<double>& y5, Deriv<double>& k7, Deriv<double>& e,
                                              double& H5, double& c5, double& s5)
 {
     constexpr int K = kGbsColumns;
-    const double a = R.a;
     double Tt[K], Tr[K], Tth[K], Tph[K], Tpr[K], Tpth[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) Tt[k] = Tr[k] = Tth[k] = Tph[k] = Tpr[k] = Tpth[k] = 0.0;
@@ -1049,10 +1067,10 @@ constexpr int kVerletMaxIter = 50;
 constexpr double kVerletTol = 1e-14;
 
 template <int KIND>
-__device__ __forceinline__ bool stages_verlet(const Ray& R, const MetricOps<KIND>& M, double h, Deriv<double>& y5,
+__device__ __forceinline__ bool stages_verlet(const Ray& R, const MetricOps<KIND>& M, Spin a, double h, Deriv<double>& y5,
                                               Deriv<double>& k7, double& H5, double& c5, double& s5)
 {
-    const double a = R.a, hh = 0.5 * h;
+    const double hh = 0.5 * h;
     Deriv<double> d;
     double Hd, cd;
     // stage 1
@@ -1139,15 +1157,18 @@ struct PairErrNorm1 {
     static constexpr double value = sum(0);
 };
 
-// Scaled error of one component with the rounding floor: zero when
-// |e| <= min(c max(|k0|, |k1|), kPairFloorTol sc), c = kPairFloorUlps ulp
-// |b - b*|_1 |h|.
+// Scaled error of one component with the rounding floor: contributes nothing
+// to the sum of squares when |e| <= min(c max(|k0|, |k1|), kPairFloorTol sc),
+// c = kPairFloorUlps ulp |b - b*|_1 |h|.  A floored ratio keeps its low word
+// and loses its high word, a subnormal below 2^-1022 whose square, and so its
+// term in sum_sq6, rounds to exactly zero: one select instead of two.
 __device__ __forceinline__ double err_ratio_floor(double e, double c, double k0, double k1, double y0, double y1,
                                                   double atol, double rtol)
 {
     const double sc = fma(rtol, max_abs(y0, y1), atol);
     const double fl = fmin(c * max_abs(k0, k1), kPairFloorTol * sc);
-    return fabs(e) <= fl ? 0.0 : e * rcp64_coarse(sc);
+    const double z = e * rcp64_coarse(sc);
+    return __hiloint2double(fabs(e) <= fl ? 0 : __double2hiint(z), __double2loint(z));
 }
 
 // y^N for a compile-time N >= 1 by repeated squaring.
@@ -1186,11 +1207,12 @@ __device__ __forceinline__ double pow_m_inv(double x)
 // of err2 clamped to [1e-24, 1e16], the range its estimate covers: at the ends
 // 0.9 err2^(-1/(2P)) is at least 11 and at most 0.17 for both P, beyond the
 // factor's own clamps, so clamping err2 never changes the factor and no branch
-// is needed.  A NaN err2 is the caller's case.
+// is needed.  fmin drops a NaN operand, so a NaN err2 clamps to the upper end
+// and gets the smallest factor, 0.2.
 template <int P>
 __device__ __forceinline__ double step_factor(double err2, double fmx)
 {
-    const double x = fmin(fmax(err2, 1e-24), 1e16);
+    const double x = fmax(fmin(err2, 1e16), 1e-24);
     return fmin(fmx, fmax(0.2, 0.9 * pow_m_inv<2 * P>(x)));
 }
 
@@ -1335,9 +1357,13 @@ __device__ __forceinline__ double pow2_floor(double x)
 
 // One attempt; returns true when the ray has terminated (outputs written).
 // (S: the extrapolation's event search; unused by the other methods.)
-template <int KIND, int PREC, int METHOD>
-__device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySettings& P, const MetricOps<KIND>& M)
+template <int KIND, int PREC, int METHOD, int SERVE>
+__device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySettings& P, const MetricOps<KIND>& M,
+                         const TraceUniform& U)
 {
+    // a one-shot trace's rays share the metric and the solver: their spin
+    // constants and radii come wave-uniform from the launch
+    const Spin K = SERVE ? spin_of(R.a) : U.spin;
     bool probe = false;
     if constexpr (METHOD == METHOD_GBS) probe = S.phase != 0;
     if (!probe && R.n_acc + R.n_rej >= P.max_steps) {
@@ -1351,7 +1377,7 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
     double fac = 1.0;
     if constexpr (METHOD == METHOD_VERLET) {
         // fixed step, no error control: a converged step is always taken
-        if (!stages_verlet<KIND>(R, M, h, y5, k7, H5, c5, s5)) {
+        if (!stages_verlet<KIND>(R, M, K, h, y5, k7, H5, c5, s5)) {
             ray_fail(R, A);
             return true;
         }
@@ -1363,16 +1389,16 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
             if (PREC == 1 && R.k32) {
                 // leaving the FP32 regime: re-evaluate the first stage in FP64
                 double Hd;
-                M.rhs_sc(R.a, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth, R.sth);
+                M.rhs_sc(K, R.r, R.th, R.pr, R.pth, R.pt, R.pph, R.k, Hd, R.cth, R.sth);
                 R.k32 = 0;
             }
             if constexpr (METHOD == METHOD_DP45)
-                stages64<KIND>(R, M, h, y5, k7, e, H5, c5, s5);
+                stages64<KIND>(R, M, K, h, y5, k7, e, H5, c5, s5);
             else if constexpr (METHOD == METHOD_GBS)
                 // one call site for attempts and probes (a probe has no error control)
-                stages64_gbs<KIND>(R, M, h, probe ? 0.0 : P.atol, probe ? 0.0 : P.rtol, y5, k7, e, H5, c5, s5);
+                stages64_gbs<KIND>(R, M, K, h, probe ? 0.0 : P.atol, probe ? 0.0 : P.rtol, y5, k7, e, H5, c5, s5);
             else
-                stages64_six<KIND, METHOD>(R, M, h, y5, k7, e, H5, c5, s5);
+                stages64_six<KIND, METHOD>(R, M, K, h, y5, k7, e, H5, c5, s5);
         }
         if constexpr (METHOD == METHOD_GBS) {
             if (probe) return gbs_probe(R, S, A, P, y5, k7, c5, s5);
@@ -1400,7 +1426,7 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
         // rejection (or for one) the step may not grow
         const bool ok = err2 <= 1.0;
         constexpr int P = METHOD == METHOD_GBS ? 2 * kGbsColumns - 1 : 5;
-        fac = isnan(err2) ? 0.2 : step_factor<P>(err2, (ok && !R.rej_prev) ? 10.0 : 1.0);
+        fac = step_factor<P>(err2, (ok && !R.rej_prev) ? 10.0 : 1.0);   // 0.2 for a NaN err2
         if constexpr (METHOD == METHOD_GBS) fac = pow2_floor(fac);
         if (!ok) {
             // rejected; a NaN or infinite error also lands here
@@ -1424,11 +1450,14 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
     // ---- constraint residual (Eq. (17)) at the accepted state
     const double aH = fabs(H5);
     R.hmax = max_abs(R.hmax, aH);   // (both non-negative)
-    if (y5.r >= 1.5 * R.rp) R.hgate = max_abs(R.hgate, aH);
+    if (y5.r >= (SERVE ? 1.5 * R.rp : U.gate_r)) R.hgate = max_abs(R.hgate, aH);
 
     // ---- events on the accepted step [lam, lam + h]
-    double r_stop = P.horizon_factor * R.rp;
-    if (KIND == 1 && A.tab_r_min > r_stop) r_stop = A.tab_r_min;
+    double r_stop = U.r_stop;
+    if constexpr (SERVE) {
+        r_stop = P.horizon_factor * R.rp;
+        if (KIND == 1 && A.tab_r_min > r_stop) r_stop = A.tab_r_min;
+    }
     const double r_esc = P.r_escape;
     const bool hz = (R.r - r_stop > 0.0) && (y5.r - r_stop <= 0.0);
     const bool es = (R.r - r_esc < 0.0) && (y5.r - r_esc >= 0.0);
@@ -1575,6 +1604,8 @@ __global__ void __launch_bounds__(256)
     GbsSearch S;
     S.phase = 0;
     RaySettings P = launch_settings(A);   // serving: each ray's request's, set with the ray
+    TraceUniform U{};
+    if constexpr (!SERVE) U = trace_uniform(A);
     bool active = false;
     bool parked = false;       // serving: this launch's epoch has ended for the lane
     bool exhausted = false;
@@ -1597,7 +1628,7 @@ __global__ void __launch_bounds__(256)
     for (;;) {
         if (__any(active)) {
             if (active) {
-                active = !ray_step<KIND, PREC, METHOD>(R, S, A, P, M);
+                active = !ray_step<KIND, PREC, METHOD, SERVE>(R, S, A, P, M, U);
                 if (!active) done = R.job;
             }
             if constexpr (SERVE) {
