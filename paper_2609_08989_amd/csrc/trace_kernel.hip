@@ -1848,37 +1848,71 @@ using namespace tartarus;
 // ---------------------------------------------------------------------------
 // cost-ordered work queue: rays nearest the critical curve are handed out first
 // ---------------------------------------------------------------------------
+// Adds each valid lane to hist[k] with one LDS atomic per distinct k in the
+// wavefront (neighbouring rays mostly share a bucket; one atomic per lane on
+// 32 counters serialised) and returns the lane's rank: the count before it,
+// in the atomic's order between wavefronts and in lane order within one.
+// Every lane of the wavefront must call it.
+__device__ __forceinline__ unsigned int wave_bucket_add(unsigned int* hist, int k, bool valid)
+{
+    unsigned long long todo = __ballot(valid);
+    unsigned int rank = 0u;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int kk = __shfl(k, leader);
+        const unsigned long long same = __ballot(valid && k == kk);
+        unsigned int base = 0u;
+        if ((int)__lane_id() == leader) base = atomicAdd(&hist[kk], (unsigned int)__popcll(same));
+        base = __shfl(base, leader);
+        if (valid && k == kk) rank = base + (unsigned int)__popcll(same & lanemask_lt());
+        todo &= ~same;
+    }
+    return rank;
+}
+
+// The passes below give each block a run of `per` consecutive rays (a
+// multiple of the block size) and keep one histogram per block in LDS: the
+// global bucket counters then take a few thousand atomics per trace instead
+// of one per bucket and 256 rays (same-address atomics serialise in L2).
+constexpr int kOrderMaxBlocks = 2048;
+
 // Pass 1: bucket of every ray (from its constants of motion) and the bucket
-// histogram.  One thread per ray; LDS histogram per block, then one global add
-// per non-empty bucket.
+// histogram.  LDS histogram per block, then one global add per non-empty
+// bucket.
 __global__ void __launch_bounds__(256) order_keys_kernel(const DevJob* jobs, const JobConst* jc, int njobs,
-                                                         long long total, unsigned char* key, unsigned int* count)
+                                                         long long total, long long per, unsigned char* key,
+                                                         unsigned int* count)
 {
     __shared__ unsigned int hist[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
     __syncthreads();
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (gid < total) {
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].ray_begin <= gid)
-                lo = mid;
-            else
-                hi = mid - 1;
+    const long long r0 = blockIdx.x * per;
+    const long long r1 = r0 + per < total ? r0 + per : total;
+    for (long long g0 = r0; g0 < r1; g0 += blockDim.x) {
+        const long long gid = g0 + threadIdx.x;
+        int k = 0;
+        if (gid < r1) {
+            int lo = 0, hi = njobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (jobs[mid].ray_begin <= gid)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const DevJob& J = jobs[lo];
+            const JobConst& C = jc[lo];
+            double al, be, p[4];
+            pixel_coords(J, gid - J.ray_begin, al, be);
+            pixel_momentum(C, J.r_obs, al, be, p);
+            // b = L / E and q = Q / E^2 are unchanged by the backward-tracing sign flip
+            const double ipt = 1.0 / p[0];
+            const double b = -p[3] * ipt;
+            const double Q = fma(p[2], p[2], C.c2_obs * (p[3] * p[3] * C.is2_obs - J.a * J.a * p[0] * p[0]));
+            k = cost_bucket(J.a, b, Q * ipt * ipt, C.rp);
+            key[gid] = (unsigned char)k;
         }
-        const DevJob& J = jobs[lo];
-        const JobConst& C = jc[lo];
-        double al, be, p[4];
-        pixel_coords(J, gid - J.ray_begin, al, be);
-        pixel_momentum(C, J.r_obs, al, be, p);
-        // b = L / E and q = Q / E^2 are unchanged by the backward-tracing sign flip
-        const double ipt = 1.0 / p[0];
-        const double b = -p[3] * ipt;
-        const double Q = fma(p[2], p[2], C.c2_obs * (p[3] * p[3] * C.is2_obs - J.a * J.a * p[0] * p[0]));
-        const int k = cost_bucket(J.a, b, Q * ipt * ipt, C.rp);
-        key[gid] = (unsigned char)k;
-        atomicAdd(&hist[k], 1u);
+        wave_bucket_add(hist, k, gid < r1);
     }
     __syncthreads();
     if (threadIdx.x < kOrderBuckets && hist[threadIdx.x]) atomicAdd(&count[threadIdx.x], hist[threadIdx.x]);
@@ -1895,26 +1929,34 @@ __global__ void order_scan_kernel(const unsigned int* count, unsigned int* curso
     }
 }
 
-// Pass 3: scatter ray indices to their bucket's range.  The order inside a
-// bucket depends on atomic timing, which only changes when a ray is traced.
+// Pass 3: scatter ray indices to their bucket's range.  A block counts its
+// run's buckets, reserves its share of each bucket's range with one global
+// atomic, then places its rays.  The order inside a bucket depends on atomic
+// timing, which only changes when a ray is traced.
 __global__ void __launch_bounds__(256) order_scatter_kernel(const unsigned char* key, unsigned int* cursor,
-                                                            long long total, unsigned int* order)
+                                                            long long total, long long per, unsigned int* order)
 {
     __shared__ unsigned int hist[kOrderBuckets], base[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
     __syncthreads();
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    int k = 0;
-    unsigned int rank = 0u;
-    if (gid < total) {
-        k = key[gid];
-        rank = atomicAdd(&hist[k], 1u);
+    const long long r0 = blockIdx.x * per;
+    const long long r1 = r0 + per < total ? r0 + per : total;
+    for (long long g0 = r0; g0 < r1; g0 += blockDim.x) {
+        const long long gid = g0 + threadIdx.x;
+        wave_bucket_add(hist, gid < r1 ? (int)key[gid] : 0, gid < r1);
     }
     __syncthreads();
-    if (threadIdx.x < kOrderBuckets && hist[threadIdx.x])
-        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x < kOrderBuckets) {
+        base[threadIdx.x] = hist[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], hist[threadIdx.x]) : 0u;
+        hist[threadIdx.x] = 0u;
+    }
     __syncthreads();
-    if (gid < total) order[base[k] + rank] = (unsigned int)gid;
+    for (long long g0 = r0; g0 < r1; g0 += blockDim.x) {
+        const long long gid = g0 + threadIdx.x;
+        const int k = gid < r1 ? (int)key[gid] : 0;
+        const unsigned int rank = wave_bucket_add(hist, k, gid < r1);
+        if (gid < r1) order[base[k] + rank] = (unsigned int)gid;
+    }
 }
 
 // The three passes; count and cursor (kOrderBuckets entries each) must be zero
@@ -1924,12 +1966,17 @@ extern "C" hipError_t tartarus_launch_order(const LaunchArgs* args, long long to
                                             hipStream_t stream)
 {
     if (total <= 0) return hipSuccess;
-    const long long blocks = (total + 255) / 256;
-    if (blocks > 0x7fffffffll || total > 0xffffffffll) return hipErrorInvalidValue;
+    if (total > 0xffffffffll) return hipErrorInvalidValue;
+    // runs of `per` rays (a multiple of 256), at most kOrderMaxBlocks of them
+    const long long groups = (total + 255) / 256;
+    const long long want = groups < kOrderMaxBlocks ? groups : kOrderMaxBlocks;
+    const long long per = (groups + want - 1) / want * 256;
+    const long long blocks = (total + per - 1) / per;
     hipLaunchKernelGGL(order_keys_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, args->jobs, args->jc,
-                       args->njobs, total, key, count);
+                       args->njobs, total, per, key, count);
     hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, stream, count, cursor);
-    hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, key, cursor, total, order);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, key, cursor, total, per,
+                       order);
     return hipGetLastError();
 }
 
