@@ -93,19 +93,26 @@ def test_requests_with_their_own_tolerance_and_precision(T):
 
 def test_arrivals_during_running_work_overlap(T):
     """A request submitted while a large one runs is admitted and finishes before it."""
-    big = stream_requests(1, seed=11, res=(384,))[0]
+    # the large one: 768^2 rays at rtol 1e-10, tens of milliseconds on the device
+    big = stream_requests(1, seed=11, res=(768,))[0]
+    big["solver"] = dict(big["solver"], rtol=1e-10, atol=1e-12)
     small = stream_requests(1, seed=12, res=(16,))[0]
-    ob = T.alloc_outputs(384 * 384)
+    ob = T.alloc_outputs(768 * 768)
     os_ = T.alloc_outputs(16 * 16)
     mk = lambda r: (T.make_metric(r["a"]), T.make_camera(r["camera"]), T.make_disk(r["disk"]),
                     T.make_solver(r["solver"]))
     tb = T.tartarus_submit(*mk(big), ob)
-    time.sleep(0.002)
+    # the small one is submitted once the large one runs (poll: 1 = running)
+    t0 = time.monotonic()
+    while T.tartarus_poll(tb) == 0 and time.monotonic() - t0 < 60.0:
+        time.sleep(0.0002)
+    assert T.tartarus_poll(tb) == 1, "the large request should still be running"
     ts = T.tartarus_submit(*mk(small), os_)
     T.tartarus_wait(ts, 120000)
     T.tartarus_wait(tb, 120000)
     sb, ss = T.tartarus_ticket_times(tb), T.tartarus_ticket_times(ts)
     assert ss[1] < sb[2]           # admitted before the large one completed
+    assert ss[2] < sb[2]           # and done before it
     ref = alone(T, small, 0)
     g = T.to_numpy(os_)
     for k in ref:
