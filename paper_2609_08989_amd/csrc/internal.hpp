@@ -123,7 +123,8 @@ struct LaunchArgs {
     int tile;                       // 1: queue positions run over 8 x 8 pixel tiles of each camera
     // queue position -> ray index (relative to first_ray); null: identity
     const unsigned int* order;
-    // serving: rays still to finish, per job-table entry (null: not counted)
+    // serving: rays still to finish, per job-table entry, one per
+    // kRemainingStride words (null: not counted)
     unsigned int* remaining;
     // tabulated metric interleaved by grid point (the integrator reads this)
     const double* table_inter;
@@ -135,6 +136,12 @@ struct LaunchArgs {
     int nseg;
     int pad3;
 };
+
+// Serving: each job-table entry's count of unfinished rays sits on a
+// 128-byte line of its own (every wavefront iteration that ends a ray
+// subtracts from its job's count; counts sharing a line made those atomics
+// contend).
+constexpr int kRemainingStride = 32;   // unsigned ints
 
 constexpr int SLOT_DOUBLES = 40;   // a parked ray (32 doubles) and its event search (8)
 

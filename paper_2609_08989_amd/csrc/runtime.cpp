@@ -650,7 +650,7 @@ struct Request {
 struct EpochBlock {
     DevJob jobs[kMaxEntries];
     alignas(256) unsigned long long head;
-    alignas(256) unsigned int remaining[kMaxEntries];
+    alignas(256) unsigned int remaining[kMaxEntries * kRemainingStride];
     int dir_job[kMaxEntries];
     long long dir_begin[kMaxEntries];
     long long seg_q[kMaxEntries + 1];
@@ -683,6 +683,12 @@ struct Server {
     hipStream_t stream = nullptr;
     EpochBlock* dblk = nullptr;
     EpochBlock* hblk = nullptr;
+    bool jobs_dirty = true;           // the host's request table differs from the device's
+    // finishing passes of the requests the last epoch completed run on fstream
+    // beside the next epoch; fin_ev marks their end, fin_pending their entries
+    hipStream_t fstream = nullptr;
+    hipEvent_t fin_ev = nullptr;
+    std::vector<int> fin_pending;
     DevJob* djobs = nullptr;
     DevJob* hjobs = nullptr;
     JobConst* djc = nullptr;
@@ -725,6 +731,10 @@ int server_alloc(int prec, int method)
     Server& S = g_srv;
     HIP_TRY(hipSetDevice(g_dev.id));
     HIP_TRY(hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&S.fstream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&S.fin_ev, hipEventDisableTiming));
+    S.fin_pending.clear();
+    S.jobs_dirty = true;
     tartarus_launch L;
     int grid = 0;
     {
@@ -772,6 +782,7 @@ void server_free()
 {
     Server& S = g_srv;
     if (S.stream) (void)hipStreamSynchronize(S.stream);
+    if (S.fstream) (void)hipStreamSynchronize(S.fstream);
     (void)hipFree(S.dblk);
     (void)hipHostFree(S.hblk);
     (void)hipFree(S.djc);
@@ -779,6 +790,10 @@ void server_free()
     (void)hipFree(S.slot_live);
     rec_pool_release(S);
     if (S.stream) (void)hipStreamDestroy(S.stream);
+    if (S.fstream) (void)hipStreamDestroy(S.fstream);
+    if (S.fin_ev) (void)hipEventDestroy(S.fin_ev);
+    S.fstream = nullptr; S.fin_ev = nullptr;
+    S.fin_pending.clear();
     S.dblk = nullptr; S.hblk = nullptr;
     S.djobs = nullptr; S.djc = nullptr; S.hjobs = nullptr; S.dremaining = nullptr; S.hremaining = nullptr;
     S.ddir_begin = nullptr; S.ddir_job = nullptr; S.hdir_begin = nullptr; S.hdir_job = nullptr;
@@ -812,7 +827,34 @@ void finish_request(Server& S, uint64_t ticket, Request& R)
     (void)ticket;
 }
 
-// One scheduling round: admit, run one epoch, collect completions.
+// Completes the requests whose finishing pass went to fstream after the last
+// epoch: waits for it, then marks them done.  Called with lk released;
+// returns with it released.
+int complete_finished(Server& S, std::unique_lock<std::mutex>& lk)
+{
+    if (S.fin_pending.empty()) return TARTARUS_OK;
+    HIP_TRY(hipEventSynchronize(S.fin_ev));
+    lk.lock();
+    for (int e : S.fin_pending) {
+        const uint64_t t = S.entry_ticket[e];
+        finish_request(S, t, S.reqs[t]);
+    }
+    S.fin_pending.clear();
+    S.jobs_dirty = true;   // finish_request resets the entries' cancel flags
+    S.done_cv.notify_all();
+    lk.unlock();
+    return TARTARUS_OK;
+}
+
+bool finishing(const Server& S, int e)
+{
+    return std::find(S.fin_pending.begin(), S.fin_pending.end(), e) != S.fin_pending.end();
+}
+
+// One scheduling round: admit, run one epoch, collect completions.  The
+// finishing passes of the requests an epoch completes run on their own stream
+// while the next epoch traces; those requests are marked done when their pass
+// has ended.
 int server_round(std::unique_lock<std::mutex>& lk)
 {
     Server& S = g_srv;
@@ -872,9 +914,9 @@ int server_round(std::unique_lock<std::mutex>& lk)
         R.t_admit = now_ns();
         S.entry_ticket[entry] = t;
         fill_job(S.hjobs[entry], &R.metric, R.cam, &R.disk, &R.solver, &R.out, R.ray_begin, 0, R.rec);
-        S.hjobs[entry].remaining = S.dremaining + entry;
+        S.hjobs[entry].remaining = S.dremaining + entry * kRemainingStride;
         S.hjobs[entry].cancelled = 0;
-        S.hremaining[entry] = (unsigned int)R.nrays;
+        S.hremaining[entry * kRemainingStride] = (unsigned int)R.nrays;
         fresh.push_back(entry);
     }
     // ---- cancellations become visible to the kernel from this epoch on
@@ -901,6 +943,17 @@ int server_round(std::unique_lock<std::mutex>& lk)
         ++nd;
     }
     if (nd == 0) return TARTARUS_OK;
+    if (!fresh.empty() || !sent.empty()) S.jobs_dirty = true;
+    // ---- nothing to trace but finishing passes in flight: wait for those
+    bool tracing = false;
+    for (int e = 0; e < kMaxEntries; ++e)
+        if (S.entry_ticket[e] && !finishing(S, e)) tracing = true;
+    if (!tracing) {
+        lk.unlock();
+        const int rc = complete_finished(S, lk);
+        lk.lock();
+        return rc;
+    }
     // ---- this epoch's queue: the unstarted rays of every live request, one
     // segment each (ordering rules in host_logic.cpp)
     std::vector<SegmentSource> live;
@@ -927,11 +980,18 @@ int server_round(std::unique_lock<std::mutex>& lk)
         if (S.entry_ticket[e] && !S.hjobs[e].cancelled && S.hjobs[e].allow32) eprec = TARTARUS_PREC_MIXED;
     lk.unlock();
 
-    // the whole epoch block in one copy: request table, head = 0, the counts
-    // (fresh entries set above, the others as read back after the last epoch),
-    // directory and segments
+    // the request table when it changed (after the finishing passes in flight,
+    // which read it), then the rest of the block in one copy: head = 0, the
+    // counts (fresh entries set above, the others as read back after the last
+    // epoch), directory and segments
+    if (S.jobs_dirty) {
+        if (!S.fin_pending.empty()) HIP_TRY(hipStreamWaitEvent(S.stream, S.fin_ev, 0));
+        HIP_TRY(hipMemcpyAsync(S.djobs, S.hjobs, sizeof(DevJob) * kMaxEntries, hipMemcpyHostToDevice, S.stream));
+        S.jobs_dirty = false;
+    }
     *S.hhead = 0ull;
-    HIP_TRY(hipMemcpyAsync(S.dblk, S.hblk, sizeof(EpochBlock), hipMemcpyHostToDevice, S.stream));
+    constexpr size_t kDown = sizeof(EpochBlock) - offsetof(EpochBlock, head);
+    HIP_TRY(hipMemcpyAsync(S.dhead, S.hhead, kDown, hipMemcpyHostToDevice, S.stream));
     LaunchArgs A;
     tartarus_metric m0;
     std::memset(&m0, 0, sizeof(m0));
@@ -963,22 +1023,25 @@ int server_round(std::unique_lock<std::mutex>& lk)
     // head and counts in one copy back (with the padding between them)
     constexpr size_t kBack = offsetof(EpochBlock, remaining) + sizeof(EpochBlock::remaining) - offsetof(EpochBlock, head);
     HIP_TRY(hipMemcpyAsync(S.hhead, S.dhead, kBack, hipMemcpyDeviceToHost, S.stream));
+    // the last epoch's completed requests, while this one traces
+    if (const int rc = complete_finished(S, lk)) return rc;
     HIP_TRY(hipStreamSynchronize(S.stream));
-    // requests whose rays have all finished: shade their disk crossings
+    // requests whose rays have all finished: their finishing pass (disk
+    // crossings, shading, outputs) on fstream; the records are complete, the
+    // stream having been synchronized
     std::vector<int> done;
     for (int e = 0; e < kMaxEntries; ++e)
-        if (S.entry_ticket[e] && S.hremaining[e] == 0) done.push_back(e);
-    for (int e : done) HIP_TRY(tartarus_launch_finish(&A, e, 1, S.hjobs[e].ray_count, S.stream));
-    if (!done.empty()) HIP_TRY(hipStreamSynchronize(S.stream));
+        if (S.entry_ticket[e] && !finishing(S, e) && S.hremaining[e * kRemainingStride] == 0) done.push_back(e);
+    if (!done.empty()) {
+        for (int e : done) HIP_TRY(tartarus_launch_finish(&A, e, 1, S.hjobs[e].ray_count, S.fstream));
+        HIP_TRY(hipEventRecord(S.fin_ev, S.fstream));
+        S.fin_pending = done;
+    }
 
     lk.lock();
     // the queue was consumed in segment order
     const std::vector<long long> used = consumed_per_segment(segv, std::min((long long)*S.hhead, total));
     for (int k = 0; k < nseg; ++k) S.reqs[S.entry_ticket[S.seg_entry[k]]].started += used[k];
-    for (int e : done) {
-        const uint64_t t = S.entry_ticket[e];
-        finish_request(S, t, S.reqs[t]);
-    }
     for (uint64_t t : sent) S.reqs[t].cancel_acked = true;
     S.done_cv.notify_all();
     return TARTARUS_OK;
@@ -1007,10 +1070,22 @@ void server_main()
         }
         int rc = server_round(lk);
         if (rc) {
+            // (a device call failed with lk released)
+            if (!lk.owns_lock()) lk.lock();
             S.dev_error = tartarus_last_error();
             S.running = false;
             S.done_cv.notify_all();
             break;
+        }
+    }
+    // finishing passes still in flight complete their requests
+    if (S.dev_error.empty() && !S.fin_pending.empty()) {
+        lk.unlock();
+        const int rc = complete_finished(S, lk);
+        lk.lock();
+        if (rc) {
+            S.dev_error = tartarus_last_error();
+            S.done_cv.notify_all();
         }
     }
 }

@@ -1552,7 +1552,7 @@ __device__ __forceinline__ void count_done(const LaunchArgs& A, int& done)
         const int leader = __ffsll((long long)m) - 1;
         const int j = __shfl(done, leader);
         const unsigned long long same = __ballot(done == j);
-        if ((int)__lane_id() == leader) atomicSub(A.remaining + j, (unsigned int)__popcll(same));
+        if ((int)__lane_id() == leader) atomicSub(A.remaining + j * kRemainingStride, (unsigned int)__popcll(same));
         if (done == j) done = -1;
         m &= ~same;
     }
