@@ -515,6 +515,45 @@ def test_gate_tolerance_fp64_sampled(T, orc):
     assert g["h_gate"][g["cls"] != 2].max() <= 1e-8
 
 
+def test_headline_configuration_sampled(T, orc):
+    """The benchmark's headline as it is timed: the 2048^2 a = 0.998 image at
+    rtol 7e-11 (the loosest listed tolerance whose |H| <= 1e-8 gate holds) in
+    the launch shape of the committed profile (256 threads x 3 blocks per CU,
+    chunk 1, refill at 4 idle lanes, cost order); 120 sampled pixels with their
+    neighbours at the FP64 bar, and the gate on every ray of the image."""
+    w = W.WORKLOADS["kerr0998_2048"]
+    sv = dict(w["solver"], rtol=7e-11, atol=7e-13)
+    launch = T.make_launch(256, 3, 1, 4, T.ORDER_COST)
+    say("case kerr0998_2048 fp64 rtol 7e-11 bench launch sampled")
+    g = gpu_trace(T, w["a"], w["cameras"][0], w["disk"], sv, launch=launch)
+    assert np.all(g["cls"] != 2)
+    assert g["h_gate"].max() <= 1e-8
+    sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], sv, 0, 120, 6, FP64_TOL, FP64_HTOL, g=g)
+
+
+@pytest.mark.parametrize("method", [1, 2], ids=["ck45", "rkf45"])
+def test_six_stage_pairs_kerr09_512_sampled(T, orc, method):
+    """Cash-Karp and Fehlberg on the full 512^2 Kerr image with the disk, as the
+    benchmark's legs trace it; 150 sampled pixels with their neighbours."""
+    w = W.WORKLOADS["kerr09_512"]
+    say("case kerr09_512 sampled method", method)
+    sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], dict(w["solver"], method=method), 0, 150, 7 + method,
+                   FP64_TOL, FP64_HTOL)
+
+
+def test_osiris_and_table1_scenes_sampled(T, orc):
+    """The paper's calibration scene (a = 0.98, edge-on, 1024^2, no disk) and its
+    Table 1 scene (Schwarzschild with the disk, D = 100) at 2048^2, as the
+    benchmark's legs trace them; sampled pixels with their neighbours."""
+    w = W.WORKLOADS["osiris_1024"]
+    say("case osiris_1024 sampled")
+    sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], w["solver"], 0, 150, 10, FP64_TOL, FP64_HTOL)
+    w = W.scaled("schwarzschild_disk_100", 2048)
+    say("case schwarzschild_disk_100 2048 sampled")
+    g, res = sampled_parity(T, orc, w["a"], w["cameras"][0], w["disk"], w["solver"], 0, 150, 11, FP64_TOL, FP64_HTOL)
+    assert res["hit_r"]["n"] >= 10   # the disk is seen in about one sample in seven
+
+
 # ------------------------------------------------------------------ tabulated metric traces
 def gpu_table(T, a, nr, nth, r_min, r_max):
     import torch
