@@ -1358,21 +1358,15 @@ __device__ __forceinline__ double pow2_floor(double x)
 // One attempt; returns true when the ray has terminated (outputs written).
 // (S: the extrapolation's event search; unused by the other methods.)
 template <int KIND, int PREC, int METHOD, int SERVE>
-__device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySettings& P0, const MetricOps<KIND>& M,
+__device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySettings& P, const MetricOps<KIND>& M,
                          const TraceUniform& U)
 {
-    // A serving ray (the extrapolation aside, whose stages use the
-    // tolerances) reads its request's settings from the job table where the
-    // attempt needs them, before (regime test) and after its stages, instead of
-    // holding them in VGPRs through the stage blocks.
-    constexpr bool kLazy = SERVE && METHOD != METHOD_GBS;
     // a one-shot trace's rays share the metric and the solver: their spin
     // constants and radii come wave-uniform from the launch
     const Spin K = SERVE ? spin_of(R.a) : U.spin;
     bool probe = false;
     if constexpr (METHOD == METHOD_GBS) probe = S.phase != 0;
-    const int max_steps = kLazy ? clamp_steps(A.jobs[R.job].max_steps) : P0.max_steps;
-    if (!probe && R.n_acc + R.n_rej >= max_steps) {
+    if (!probe && R.n_acc + R.n_rej >= P.max_steps) {
         ray_fail(R, A);
         return true;
     }
@@ -1381,25 +1375,14 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
     double H5, c5, s5;
     bool used32 = false;
     double fac = 1.0;
-    RaySettings P = P0;
-    // (the job index passes through an empty asm that takes the step's end, so
-    // the loads cannot be hoisted into the stages)
-    auto settings_now = [&]() {
-        if constexpr (kLazy) {
-            int j = R.job;
-            asm volatile("" : "+v"(j) : "v"(y5.r));
-            P = job_settings(A.jobs[j]);
-        }
-    };
     if constexpr (METHOD == METHOD_VERLET) {
         // fixed step, no error control: a converged step is always taken
         if (!stages_verlet<KIND>(R, M, K, h, y5, k7, H5, c5, s5)) {
             ray_fail(R, A);
             return true;
         }
-        settings_now();
     } else {
-        if (PREC == 1 && KIND == 0 && far_field(R, A, kLazy ? job_settings(A.jobs[R.job]) : P0)) {
+        if (PREC == 1 && KIND == 0 && far_field(R, A, P)) {
             stages32(R, h, y5, k7, e, H5, c5, s5);
             used32 = true;
         } else {
@@ -1413,15 +1396,14 @@ __device__ bool ray_step(Ray& R, GbsSearch& S, const LaunchArgs& A, const RaySet
                 stages64<KIND>(R, M, K, h, y5, k7, e, H5, c5, s5);
             else if constexpr (METHOD == METHOD_GBS)
                 // one call site for attempts and probes (a probe has no error control)
-                stages64_gbs<KIND>(R, M, K, h, probe ? 0.0 : P0.atol, probe ? 0.0 : P0.rtol, y5, k7, e, H5, c5, s5);
+                stages64_gbs<KIND>(R, M, K, h, probe ? 0.0 : P.atol, probe ? 0.0 : P.rtol, y5, k7, e, H5, c5, s5);
             else
                 stages64_six<KIND, METHOD>(R, M, K, h, y5, k7, e, H5, c5, s5);
         }
         if constexpr (METHOD == METHOD_GBS) {
-            if (probe) return gbs_probe(R, S, A, P0, y5, k7, c5, s5);
+            if (probe) return gbs_probe(R, S, A, P, y5, k7, c5, s5);
         }
         R.n_f32 += used32 ? 1 : 0;
-        settings_now();
         const double atol = P.atol, rtol = P.rtol;
         double acc;
         if constexpr (METHOD == METHOD_GBS) {
@@ -1579,18 +1561,18 @@ __device__ __forceinline__ void count_done(const LaunchArgs& A, int& done)
 // SERVE = 1: the serving epochs' instance, which resumes parked rays, parks
 // those that use up the epoch's attempt budget and counts finished rays down per
 // request; SERVE = 0: one-shot traces, without that machinery (a ray that can
-// be parked at any iteration keeps every field of its state live: 166 VGPRs
-// against 152 for the Dormand-Prince FP64 instance).
+// be parked at any iteration keeps every field of its state live, 190 VGPRs
+// against 160 for the Dormand-Prince FP64 instance).
 //
-// Occupancy target: 3 waves per SIMD (up to 168 VGPRs) for the analytic
-// instances of the pairs and Verlet, one-shot and serving alike, which all fit
-// without VGPR spills; 2 (up to 256) for the extrapolation and the tabulated
-// metric.  One wave per SIMD is fastest on small images (a lone wavefront keeps
-// the long rays' critical path short); more give large images more
-// throughput.  The autotuner picks.
+// Occupancy target: at most 2 waves per SIMD (up to 256 VGPRs), or 3 (168) for
+// the one-shot analytic Dormand-Prince instances: the FP64 one fits without
+// spills; the mixed one spills 13 VGPRs outside its stage blocks and still runs
+// 6 % faster at 3 waves than at 2 on a 2048x2048 image.  One wave per SIMD is
+// fastest on small images (a lone wavefront keeps the long rays' critical path
+// short); more give large images more throughput.  The autotuner picks.
 template <int KIND, int PREC, int METHOD, int SERVE>
 struct WavesPerEU {
-    static constexpr int value = (KIND == 0 && METHOD != METHOD_GBS) ? 3 : 2;
+    static constexpr int value = (!SERVE && KIND == 0 && METHOD == METHOD_DP45) ? 3 : 2;
 };
 
 template <int KIND, int PREC, int METHOD, int SERVE>
