@@ -444,6 +444,8 @@ def main():
     ap.add_argument("--only-tabulated", action="store_true",
                     help="trace the 64-camera tabulated batch only (for profilers)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-latency leg")
+    ap.add_argument("--only-serving", action="store_true",
+                    help="run the serving-latency leg only (for profilers), at --rtol or the headline's gate 7e-11")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one device copy of this many MiB (calibrates FETCH_SIZE / WRITE_SIZE)")
@@ -470,6 +472,10 @@ def main():
         return
 
     T.tartarus_init(0, 0)
+    if args.only_serving:
+        rec = serving_leg(T, torch, W, n_requests=args.serving_requests, rtol=args.rtol or 7e-11)
+        print(json.dumps({"only_serving": rec}))
+        return
     if args.only_tabulated:
         S, launch = tabulated_scene(T, torch, W)
         rec = leg_record(T, torch, S, S.args(), args.steps, args.warmup, launch)
