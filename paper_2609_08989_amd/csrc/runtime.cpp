@@ -839,8 +839,10 @@ int complete_finished(Server& S, std::unique_lock<std::mutex>& lk)
         const uint64_t t = S.entry_ticket[e];
         finish_request(S, t, S.reqs[t]);
     }
+    // (finish_request clears the entries' cancel flags on the host only: a
+    // freed entry is not read on the device until an admission refills it,
+    // which marks the table for copying)
     S.fin_pending.clear();
-    S.jobs_dirty = true;   // finish_request resets the entries' cancel flags
     S.done_cv.notify_all();
     lk.unlock();
     return TARTARUS_OK;
