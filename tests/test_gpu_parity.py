@@ -600,17 +600,19 @@ def test_tabulated_vs_analytic_on_gpu(T, orc):
 
 
 def test_tabulated_64_cameras_sampled(T, orc):
-    """All 64 cameras (512^2 each) in one launch; 400 sampled pixels and their 8
-    neighbours traced by the oracle.  Classes must be identical off the edge
-    band (a sample with a neighbour of another oracle class); every class
-    difference must lie in that band; values on matching off-band samples
-    within the tabulated bar."""
+    """All 64 cameras (512^2 each) in one launch, in the launch shape the
+    benchmark times (256 threads x 2 blocks per CU, pixel order); 400 sampled
+    pixels and their 8 neighbours traced by the oracle.  Classes must be
+    identical off the edge band (a sample with a neighbour of another oracle
+    class); every class difference must lie in that band; values on matching
+    off-band samples within the tabulated bar."""
     w, a, nr, nth, r_min, r_max = c5_setup(orc)
     tab_g = gpu_table(T, a, nr, nth, r_min, r_max)
     tab_o = orc.build_kerr_table(a, nr, nth, r_min, r_max)
     cams = w["cameras"]
     say("case tabulated 64 cameras x 512^2 fp64")
-    g = gpu_trace(T, a, cams, w["disk"], w["solver"], table=(tab_g, nr, nth, r_min, r_max))
+    g = gpu_trace(T, a, cams, w["disk"], w["solver"], table=(tab_g, nr, nth, r_min, r_max),
+                  launch=T.make_launch(256, 2, 1, 4, T.ORDER_PIXEL))
     nx = ny = 512
     per = nx * ny
     nsample = 400
