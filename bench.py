@@ -313,7 +313,7 @@ def method_legs(T, torch, W, steps, gate_rtol_c2) -> dict:
     for mname, mcode in (("ck45", T.METHOD_CK45), ("rkf45", T.METHOD_RKF45)):
         log("bench: leg", mname)
         legs[f"kerr09_512_{mname}_rtol1e-8"] = leg_record(T, torch, S, S.args(1e-8, 0, method=mcode), steps, 2)
-    for mname, rtol in (("gbs_rtol1e-8", 1e-8), ("gbs_gate", gate_rtol_c2), ("gbs_rtol1e-12", 1e-12),
+    for mname, rtol in (("gbs_rtol1e-8", 1e-8), ("gbs_at_dp45_gate_rtol", gate_rtol_c2), ("gbs_rtol1e-12", 1e-12),
                         ("fp64_rtol1e-12", 1e-12)):
         log("bench: leg", mname)
         kw = {"method": T.METHOD_GBS} if mname.startswith("gbs") else {}
