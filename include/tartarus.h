@@ -312,8 +312,9 @@ int tartarus_build_kerr_table(double a, int nr, int nth, double r_min, double r_
  * are bit-identical to tartarus_trace of the same request alone.  Tolerances,
  * step settings and precision are the request's own; the integration method
  * is the session's (the first request's: a request with another method gets
- * E_INVALID).  Output buffers must stay alive until poll reports done or
- * cancel returns. */
+ * E_INVALID).  Requests use the analytic Kerr metric (a tabulated metric gets
+ * E_INVALID; trace it with tartarus_trace).  Output buffers must stay alive
+ * until poll reports done or cancel returns. */
 
 /* Hand-out order of the serving queue's unstarted rays, applied from the next
  * epoch on: TARTARUS_SERVE_SMALLEST_FIRST (default) gives lanes to the rays of

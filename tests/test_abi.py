@@ -93,6 +93,11 @@ def test_table_metric_rules(T):
     s.precision = T.PREC_MIXED
     assert T.tartarus_validate(m, c, d, s) == T.E_INVALID  # tables are FP64 only
     s.precision = T.PREC_FP64
+    # serving takes analytic Kerr requests only; the refusal needs no device
+    fake = {f: type("P", (), {"data_ptr": lambda self: 0x1000})() for f in T.OUTPUT_FIELDS}
+    so, t = T.outputs_struct(fake), C.c_uint64(0)
+    assert T.lib().tartarus_submit(C.byref(m), C.byref(c), C.byref(d), C.byref(s), C.byref(so),
+                                   C.byref(t)) == T.E_INVALID
     m.r_max = 1.0
     assert T.tartarus_validate(m, c, d, s) == T.E_INVALID
 
