@@ -599,6 +599,26 @@ def test_tabulated_vs_analytic_on_gpu(T, orc):
     assert res["hit_r"]["max"] < 1e-5 and res["hit_g"]["max"] < 1e-5
 
 
+def test_launch_shape_invariance_tabulated(T, orc):
+    """The tabulated integrator on three ragged cameras: the same bits for every
+    launch shape and queue order (each lane gathers its own table cells and
+    shares no arithmetic with its neighbours)."""
+    w, a, nr, nth, r_min, r_max = c5_setup(orc)
+    tab = gpu_table(T, a, nr, nth, r_min, r_max)
+    cams = [dict(w["cameras"][c], nx=53, ny=37) for c in (5, 31, 58)]
+    say("case tabulated launch shapes, 3 cameras 53x37")
+    ref = gpu_trace(T, a, cams, w["disk"], w["solver"], table=(tab, nr, nth, r_min, r_max),
+                    launch=T.make_launch(order=T.ORDER_PIXEL))
+    assert (ref["n_hits"] > 0).any() and (ref["cls"] == 1).any()
+    for shape in ((64, 2, 16, 1, T.ORDER_COST), (256, 1, 1, 4, T.ORDER_TILE), (128, 0, 64, 8, T.ORDER_DEFAULT),
+                  (256, 2, 1, 4, T.ORDER_PIXEL)):
+        say("tabulated launch", shape)
+        g = gpu_trace(T, a, cams, w["disk"], w["solver"], table=(tab, nr, nth, r_min, r_max),
+                      launch=T.make_launch(*shape))
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (shape, k)
+
+
 def test_tabulated_64_cameras_sampled(T, orc):
     """All 64 cameras (512^2 each) in one launch, in the launch shape the
     benchmark times (256 threads x 2 blocks per CU, pixel order); 400 sampled
